@@ -1,0 +1,176 @@
+"""Benchmark: closed-loop Monte Carlo of the stochastic CSTR on one MI355X.
+
+One step = one whole campaign of the paper-scale workload (30,000 NMPC +
+30,000 PI closed loops on shared Philox noise, L = 600, Ns = 20, N = 60,
+Nc = 5, FP64): every sample's plant, estimator and controller, then the Phi
+statistics.  Inputs are seeded and synthetic; nothing crosses PCIe inside the
+timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CU x 128 FP64 FLOP/clk x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c1")
+    ap.add_argument("--samples", type=int, default=0, help="override n_samples (development)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the adjoint-vs-plain comparison")
+    ap.add_argument("--plain-samples", type=int, default=3000)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, seconds):
+    """The oracle, as it stands, on the host cores: NMPC closed loops of the
+    same workload, sample ids 0, 1, ... until about `seconds` of wall time."""
+    import numpy as np
+
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    n_nmpc = cfg["kind_split"] if cfg["kind_split"] >= 0 else cfg["n_samples"]
+    done, wall, batch, start = 0, 0.0, cores, 0
+    while wall < seconds and start < n_nmpc:
+        ids = np.arange(start, min(start + batch, n_nmpc), dtype=np.int64)
+        t0 = time.perf_counter()
+        oracle.run(cfg, ids=ids, nthreads=cores)
+        wall += time.perf_counter() - t0
+        done += len(ids)
+        start += len(ids)
+    return dict(value=done / wall, unit="NMPC closed-loop sims/s", cores=cores, kind="oracle",
+                sample=f"NMPC sample ids 0..{done - 1} of the same workload ({done} closed loops, "
+                       f"{wall:.1f} s wall on {cores} threads)")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; --gpus above 1 is not supported "
+              "(samples are independent: a multi-GPU campaign shards sample ids)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2212_02197_amd import binding, workloads
+    torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", 0)))
+    cfg = workloads.CONFIGS[args.config]()
+    if args.samples:
+        cfg["n_samples"] = args.samples
+        if cfg["kind_split"] >= 0:
+            cfg["kind_split"] = args.samples // 2
+            cfg["noise_mod"] = args.samples // 2
+    S = cfg["n_samples"]
+    camp = binding.Campaign(cfg)
+    for _ in range(args.warmup):
+        camp.run()
+        camp.costs()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        camp.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phi, stats = camp.costs()
+    ms_kernels = camp.kernel_ms()
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    n_nmpc, n_pi = stats["count"]
+    value = n_nmpc / (ms_per_step / 1000.0) if n_nmpc else S / (ms_per_step / 1000.0)
+    tot = stats["totals"]
+    plan = camp.plan()
+    # dominant kernel: the NMPC closed loop.  Algorithmic FP64 work of its
+    # samples (per-sample table x counters, summed on the device) over its
+    # duration from HIP events on the launch stream (last timed step).
+    nmpc_flops = stats["flops_by_kind"][0]
+    nmpc_ms = ms_kernels[0]
+    roofline = None
+    if n_nmpc and nmpc_ms > 0:
+        achieved = nmpc_flops / (nmpc_ms / 1000.0) / 1e12
+        roofline = dict(bound="alu", achieved=round(achieved, 4),
+                        peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                        frac=round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5), traffic=None)
+    camp_flops = stats["flops_algorithmic"]
+    camp.close()
+
+    plain = None
+    if not args.no_plain and n_nmpc:
+        plain = adjoint_vs_plain(cfg, args.plain_samples)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, args.cpu_seconds)
+
+    out = {
+        "metric": "NMPC CSTR closed-loop sims/sec on 1 GPU; % FP64 peak; adjoint vs plain SQP",
+        "value": round(value, 3),
+        "unit": "NMPC closed-loop sims/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.config}: {S} samples ({n_nmpc} NMPC N={cfg['N']} + {n_pi} PI), "
+                               f"L={cfg['L']}, Ns={cfg['Ns']}, Nc={cfg['Nc']}, seed={cfg['seed']}, "
+                               f"SQP eps={cfg['sqp_eps']}, adjoint gradient",
+                   "samples": S, "nmpc_samples": n_nmpc, "pi_samples": n_pi},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "all_sims_per_s": round(S / (ms_per_step / 1000.0), 3),
+        "kernel_ms": {"nmpc": round(ms_kernels[0], 3), "pi": round(ms_kernels[1], 3),
+                      "stats": round(ms_kernels[2], 3)},
+        "ocp": {"total": tot["n_ocp"], "failed": tot["n_ocp_fail"],
+                "sqp_iter_per_ocp": round(tot["sqp_iter"] / max(1, tot["n_ocp"]), 3),
+                "ipm_iter_per_sqp": round(tot["ipm_iter"] / max(1, tot["sqp_iter"]), 3)},
+        "phi": {"mean_nmpc": stats["mean"][0], "var_nmpc": stats["var"][0],
+                "mean_pi": stats["mean"][1], "var_pi": stats["var"][1]},
+        "launch_plan": plan,
+        "adjoint_vs_plain": plain,
+        "algorithmic_gflop_per_step": round(camp_flops / 1e9, 3),
+    }
+    print(json.dumps(out))
+
+
+def adjoint_vs_plain(cfg, n):
+    """Same NMPC samples (ids 0..n-1) solved with the adjoint gradient and
+    with plain forward sensitivities at equal KKT tolerance."""
+    import numpy as np
+    import torch
+
+    from paper_2212_02197_amd import binding
+    res = {}
+    phis = {}
+    for mode, name in ((1, "adjoint"), (0, "plain")):
+        c = dict(cfg, n_samples=n, kind_split=-1, default_kind=0, noise_mod=0, grad_mode=mode)
+        camp = binding.Campaign(c)
+        camp.run()
+        camp.costs()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        camp.run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        phi, st = camp.costs()
+        ps = camp.per_sample()
+        phis[name] = (phi, ps["ashash"])
+        res[name] = dict(sims_per_s=round(n / dt, 3), nmpc_kernel_ms=round(camp.kernel_ms()[0], 3),
+                         sqp_iter_per_ocp=round(st["totals"]["sqp_iter"] / st["totals"]["n_ocp"], 3))
+        camp.close()
+    rel = np.abs(phis["adjoint"][0] - phis["plain"][0]) / np.abs(phis["plain"][0])
+    res["samples"] = n
+    res["speedup_adjoint_over_plain"] = round(res["adjoint"]["sims_per_s"] / res["plain"]["sims_per_s"], 4)
+    res["max_rel_phi_diff"] = float(rel.max())
+    res["active_set_flips"] = int((phis["adjoint"][1] != phis["plain"][1]).sum())
+    return res
+
+
+if __name__ == "__main__":
+    main()

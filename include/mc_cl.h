@@ -1,0 +1,209 @@
+/*
+ * mc_cl.h -- C-ABI of the MI355X (gfx950) Monte Carlo closed-loop library.
+ *
+ * Method: Kaysfeld, Zanon, Joergensen, "Performance Quantification of a
+ * Nonlinear Model Predictive Controller by Parallel Monte Carlo Simulations
+ * of a Closed-loop System" (arXiv 2212.02197).  Every sample integrates the
+ * stochastic continuous-discrete CSTR (CDS section, eq. (CDS); Model section,
+ * eq. (CSTR)) by Euler-Maruyama sub-steps, runs the CD-EKF (NMPC section,
+ * eq. (predictionEquations) and eq. (Josph)), applies either the NMPC (OCP of
+ * eq. (OPC_general) by single-shooting SQP: QP subproblem, Armijo line search
+ * eq. (Armijo), damped BFGS, scaled KKT test eq. (convergence)) or the PI law
+ * eq. (PI), and accumulates its cost eq. (Phi).
+ *
+ * Conventions
+ *  - All arithmetic is FP64.  Units: L, s, K, mol; plant flow F in L/s; NMPC
+ *    decision inputs u in mL/min (Results section: 0 <= u <= 1000 mL/min).
+ *  - Functions return an int status: MC_CL_OK (0) or a negative MC_CL_E*.
+ *  - Per-sample numerical events (SQP iteration cap, line-search cap, BFGS
+ *    reset, non-finite state) are data in the outputs, never errors.
+ *  - Device pointers are HIP device addresses on the context's device; host
+ *    pointers are ordinary CPU memory.  The library never frees caller memory.
+ *  - Thread safety: one context must not be used from two threads at once;
+ *    different contexts are independent.
+ */
+#ifndef MC_CL_H
+#define MC_CL_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MC_CL_ABI_VERSION 1u
+#define MC_CL_SPMAX 8        /* setpoint schedule levels                        */
+#define MC_CL_NMAX 64        /* largest NMPC horizon                            */
+#define MC_CL_NHIST 202      /* histogram: underflow, 200 bins, overflow        */
+
+enum {
+    MC_CL_OK = 0,
+    MC_CL_EINVAL = -1,       /* bad argument / parameter out of its domain      */
+    MC_CL_EHIP = -2,         /* HIP runtime error (text kept for strerror)      */
+    MC_CL_ENOMEM = -3,       /* device allocation failed                        */
+    MC_CL_ESTATE = -4,       /* call out of order (costs before run, ...)       */
+    MC_CL_EUNSUPPORTED = -5  /* valid request this build does not handle        */
+};
+
+/* Per-sample counter rows of mc_cl_outputs.counters ([MC_CL_NCNT][S]).      */
+enum {
+    MC_CL_CNT_KIND = 0,      /* 0 NMPC, 1 PI                                    */
+    MC_CL_CNT_N,             /* horizon                                         */
+    MC_CL_CNT_L,             /* closed-loop intervals                           */
+    MC_CL_CNT_OCP,           /* OCPs solved (= L for NMPC; Table I)             */
+    MC_CL_CNT_OCP_FAIL,      /* OCPs that hit the SQP iteration cap             */
+    MC_CL_CNT_SQP_ITER,      /* SQP iterations (QP solves)                      */
+    MC_CL_CNT_IPM_ITER,      /* interior-point iterations                       */
+    MC_CL_CNT_LS_TRIALS,     /* shooting evaluations of the objective           */
+    MC_CL_CNT_LS_CAP,        /* line searches that hit the backtrack cap        */
+    MC_CL_CNT_BFGS_SKIP,     /* BFGS updates skipped (kappa <= eps_m)           */
+    MC_CL_CNT_BFGS_RESET,    /* W reset to I after a non-positive pivot         */
+    MC_CL_CNT_IPM_CAP,       /* QPs that hit the interior-point iteration cap   */
+    MC_CL_CNT_NONFINITE,     /* 1 if a non-finite state appeared                */
+    MC_CL_CNT_GRAD,          /* objective-gradient evaluations                  */
+    MC_CL_CNT_AS_ITER,       /* active-set QP iterations (factorisations)       */
+    MC_CL_NCNT
+};
+
+/*
+ * Campaign parameters.  The caller owns it; mc_cl_create copies it.
+ * Set struct_size = sizeof(mc_cl_params) and abi_version = MC_CL_ABI_VERSION.
+ */
+typedef struct {
+    uint32_t struct_size, abi_version;
+    /* plant, eq. (CSTR): V (L), k0 (L/(mol s)), Ea/R (K), beta (K L/mol),
+     * inlet concentrations (mol/L) and temperature (K)                      */
+    double V, k0, EaR, beta, cAin, cBin, cTin;
+    double sigma[3];          /* diffusion diag(sigma_A, sigma_B, sigma_T)    */
+    double Rmeas;             /* measurement variance of y = c_T + v (K^2)    */
+    double Ts;                /* sampling time (s)                            */
+    int32_t Ns;               /* Euler-Maruyama sub-steps per interval        */
+    int32_t L;                /* closed-loop intervals N-bar (Phi has L+1)    */
+    /* setpoint zbar(t_i), t_i = i Ts: level sp_z[j] from interval sp_i[j]
+     * (sp_i[0] = 0, increasing), periodic with sp_period intervals if > 0;
+     * optional per-sample step zbar *= (1 + sign sp_step_rel) from interval
+     * istep ~ U{sp_step_lo..sp_step_hi}, sign a fair coin                    */
+    int32_t n_sp, sp_period;
+    int32_t sp_i[MC_CL_SPMAX];
+    double sp_z[MC_CL_SPMAX];
+    double sp_step_rel;
+    int32_t sp_step_lo, sp_step_hi;
+    /* NMPC: horizon N (1..64), RK4 steps per interval Nc, output weight Qz,
+     * input bounds (mL/min)                                                  */
+    int32_t N, Nc;
+    double Qz, umin, umax;
+    /* SQP: KKT tolerance, Armijo c1, backtracking factor                     */
+    double sqp_eps, ls_c1, ls_beta;
+    int32_t sqp_max_iter, ls_max_bt;
+    int32_t grad_mode;        /* 0 forward sensitivities, 1 adjoint           */
+    int32_t ipm_max_iter;     /* interior-point iteration cap of the QP       */
+    /* PI, eq. (PI); flow in L/s, clip bounds pi_umin..pi_umax                */
+    double kP, kI, kaw, pi_umin, pi_umax;
+    /* CD-EKF initial covariance P_{-1|-1}; initial-state mode:
+     * x0_mode 0: n0 = C_in V, x-hat = c_T,in V (Results section)
+     * x0_mode 1: n0 = n_ss(zbar(0)) (1 + x0_rel_std xi), x-hat = n_ss,T      */
+    double P0, x0_rel_std;
+    int32_t x0_mode;
+    int32_t kind_split;       /* >= 0: ids < split are NMPC, others PI         */
+    int32_t default_kind;     /* kind when kind_split < 0 (0 NMPC, 1 PI)       */
+    int32_t run_ekf_for_pi;   /* run the estimator for PI samples too          */
+    /* Monte Carlo                                                            */
+    uint64_t seed;            /* Philox key                                    */
+    int64_t noise_mod;        /* noise id = sample id mod noise_mod (0: id)    */
+    int64_t n_samples;        /* S >= 1                                        */
+    int64_t sample_id_offset; /* first sample id (chunking, subsets)           */
+    int32_t n_horizon_choices;/* > 0: N ~ U{horizon_choices[0..n-1]} per sample */
+    int32_t horizon_choices[4];
+    int32_t L_lo, L_hi;       /* L_lo < L_hi: L ~ U{L_lo..L_hi} per sample      */
+    double kin_lognorm_sigma; /* > 0: plant k0, Ea/R times exp(sigma xi)        */
+    int32_t hess_warm;        /* 1: OCP i+1 starts from OCP i's W shifted       */
+    int32_t want_grad;        /* PI: keep checkpoints for mc_cl_grad            */
+    double noise_scale;       /* 1 stochastic, 0 deterministic run             */
+    int32_t ckpt_interval;    /* PI reverse pass: intervals per checkpoint (0 = auto) */
+    int32_t samples_per_wave; /* NMPC lanes used per wavefront (0 = auto)       */
+    /* QP solver: 0 primal-dual interior point (the paper's method family);
+     * 1 primal-dual active set warm-started from the SQP multipliers, with
+     * the interior-point method as fallback when the active set has not
+     * settled after 8 factorisations.  Both return the QP's unique minimiser. */
+    int32_t qp_solver;
+    int32_t reserved0;
+} mc_cl_params;
+
+/* Optional outputs of mc_cl_run; every pointer may be NULL.  All are device
+ * pointers on the context's device, written asynchronously on the stream.
+ * Layout is structure-of-arrays over samples, sample s at column s.         */
+typedef struct {
+    double *phi;              /* [S] eq. (Phi)                                 */
+    int32_t *counters;        /* [MC_CL_NCNT][S]                               */
+    uint64_t *ashash;         /* [S] FNV-1a-64 over (i, active-set bitmask) of
+                                 every OCP; bit k set if u_k is within 1e-6 of
+                                 a bound at the implemented solution           */
+    double *traj_z;           /* [L+1][S] output z = c_T (K); needs uniform L  */
+    double *traj_u;           /* [L][S] implemented flow (L/s)                 */
+    double *traj_xhat;        /* [L][S] filtered estimate x-hat_{i|i}          */
+} mc_cl_outputs;
+
+/* Campaign statistics (per controller: index 0 NMPC, 1 PI).                 */
+typedef struct {
+    int64_t count[2];
+    double mean[2];           /* mean Phi                                      */
+    double var[2];            /* sample variance of Phi (divisor count - 1)    */
+    int64_t hist[2][MC_CL_NHIST]; /* log10 Phi in 200 bins on [-4, 4),
+                                     [0] underflow, [201] overflow             */
+    int64_t totals[MC_CL_NCNT];   /* column sums of the counters               */
+    double flops_algorithmic; /* FP64 work of the campaign by the per-routine
+                                 table times the counters                      */
+    double flops_by_kind[2];  /* the same split by controller (NMPC, PI)      */
+    size_t workspace_bytes;   /* device memory the context holds               */
+} mc_cl_stats;
+
+typedef struct mc_cl_ctx mc_cl_ctx;   /* opaque, library-owned                */
+
+/* Validate parameters, pick the launch plan, allocate device workspaces on
+ * the current HIP device.  EINVAL on out-of-domain parameters (non-finite
+ * values, V <= 0, N outside 1..64, umin > umax, S < 1, ...), ENOMEM,
+ * EHIP.  *out is set only on MC_CL_OK.                                       */
+int mc_cl_create(const mc_cl_params *p, mc_cl_ctx **out);
+
+/* Run the campaign asynchronously on hip_stream (a hipStream_t; NULL = the
+ * null stream): every sample's closed loop, then the Phi statistics.  Results
+ * stay in the context; `o` (may be NULL) names extra device outputs.
+ * ESTATE if trajectories are requested with per-sample L.                   */
+int mc_cl_run(mc_cl_ctx *c, void *hip_stream, const mc_cl_outputs *o);
+
+/* Wait for the last run, then copy Phi ([S], host, may be NULL) and the
+ * statistics (host, may be NULL).  ESTATE before any run.                   */
+int mc_cl_costs(mc_cl_ctx *c, double *phi_host, mc_cl_stats *st);
+
+/* PI samples only: gradient of mean Phi over the PI samples w.r.t.
+ * theta = (Kc, tau_i), kP = Kc, kI = Kc / tau_i, by the reverse pass through
+ * the whole closed loop from plant-state checkpoints (noise held fixed).
+ * g (host, 2 doubles) receives d mean Phi / d theta after the stream is
+ * synchronised; per_sample (device, [2][S], may be NULL) receives each
+ * sample's dPhi/dtheta (0 for NMPC samples).  ESTATE without a previous run
+ * with want_grad = 1 or with no PI sample.                                  */
+int mc_cl_grad(mc_cl_ctx *c, void *hip_stream, double g[2], double *per_sample);
+
+/* Release the context and its device memory (waits for its work).          */
+void mc_cl_destroy(mc_cl_ctx *c);
+
+/* Static text for a status code (for MC_CL_EHIP: the last HIP error text).  */
+const char *mc_cl_strerror(int status);
+
+/* Version of the ABI this library implements.                              */
+uint32_t mc_cl_abi_version(void);
+
+/* Diagnostics.
+ * mc_cl_kernel_ms: device time (ms, HIP events on the run's stream) of the
+ * last run's NMPC kernels [0], PI kernel [1], statistics [2] and of the last
+ * mc_cl_grad reverse pass [3]; waits for the run.  ESTATE before a run.
+ * mc_cl_plan: launch plan of the NMPC horizon classes, 5 ints per class
+ * {NMAX, samples, samples per wavefront, work groups, resident wavefronts};
+ * returns the number of classes written (<= max_classes).                   */
+int mc_cl_kernel_ms(mc_cl_ctx *c, float ms[4]);
+int mc_cl_plan(mc_cl_ctx *c, int32_t *out, int max_classes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MC_CL_H */

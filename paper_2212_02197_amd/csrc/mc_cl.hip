@@ -1,0 +1,515 @@
+// mc_cl.hip -- host runtime and C-ABI of the MI355X Monte Carlo closed-loop
+// library (see include/mc_cl.h).  Plans a campaign (per-sample kind, horizon
+// and length drawn on the device, NMPC samples grouped by horizon class and
+// sorted by work), sizes the persistent NMPC launch from the occupancy the
+// kernel reaches, owns the device workspaces and launches every step of the
+// path on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "mc_cl.h"
+#include "mc_kernels.hpp"
+
+using namespace mccl;
+
+namespace {
+
+thread_local std::string g_hip_error;
+
+#define HIPCHK(expr)                                                        \
+    do {                                                                    \
+        hipError_t e_ = (expr);                                             \
+        if (e_ != hipSuccess) {                                             \
+            g_hip_error = std::string(#expr) + ": " + hipGetErrorString(e_); \
+            return e_ == hipErrorOutOfMemory ? MC_CL_ENOMEM : MC_CL_EHIP;   \
+        }                                                                   \
+    } while (0)
+
+// Per-sample plan: kind, horizon and length (device-drawn, as the kernels).
+__global__ void plan_kernel(DevParams p, int64_t S, int32_t* kind, int32_t* N, int32_t* L) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= S) return;
+    const Setup s = sample_setup(p, p.id_offset + t);
+    kind[t] = s.kind;
+    N[t] = s.N;
+    L[t] = s.L;
+}
+
+__global__ void fill_i32(int* a, int n, int v) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) a[t] = v;
+}
+__global__ void fill_u64(unsigned long long* a, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) a[t] = 0ull;
+}
+
+struct NmpcClass {
+    int nmax = 0;
+    int64_t count = 0;
+    int spw = 64, groups = 0, slots = 0;
+    int64_t* d_pos = nullptr;
+    double* d_tiles = nullptr;
+    double* d_xs = nullptr;
+    double* d_W = nullptr;
+    int64_t tile_stride = 0, xs_stride = 0, w_stride = 0;
+};
+
+template <int NMAX, int GMODE>
+hipError_t launch_nmpc(const DevParams& dp, const NmpcWork& wk, const Outs& o, int slots,
+                       hipStream_t st) {
+    hipLaunchKernelGGL((nmpc_kernel<NMAX, GMODE>), dim3(slots), dim3(64), 0, st, dp, wk, o);
+    return hipGetLastError();
+}
+
+template <int NMAX, int GMODE>
+int max_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, nmpc_kernel<NMAX, GMODE>, 64, 0) !=
+        hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+int blocks_per_cu(int nmax, int gmode) {
+    if (gmode == 1) {
+        if (nmax == 16) return max_blocks_per_cu<16, 1>();
+        if (nmax == 32) return max_blocks_per_cu<32, 1>();
+        return max_blocks_per_cu<64, 1>();
+    }
+    if (nmax == 16) return max_blocks_per_cu<16, 0>();
+    if (nmax == 32) return max_blocks_per_cu<32, 0>();
+    return max_blocks_per_cu<64, 0>();
+}
+
+hipError_t dispatch_nmpc(int nmax, int gmode, const DevParams& dp, const NmpcWork& wk,
+                         const Outs& o, int slots, hipStream_t st) {
+    if (gmode == 1) {
+        if (nmax == 16) return launch_nmpc<16, 1>(dp, wk, o, slots, st);
+        if (nmax == 32) return launch_nmpc<32, 1>(dp, wk, o, slots, st);
+        return launch_nmpc<64, 1>(dp, wk, o, slots, st);
+    }
+    if (nmax == 16) return launch_nmpc<16, 0>(dp, wk, o, slots, st);
+    if (nmax == 32) return launch_nmpc<32, 0>(dp, wk, o, slots, st);
+    return launch_nmpc<64, 0>(dp, wk, o, slots, st);
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+struct mc_cl_ctx {
+    mc_cl_params prm{};
+    DevParams dp{};
+    int device = 0;
+    int n_cu = 0;
+    int64_t S = 0;
+    int64_t n_pi = 0, n_nmpc = 0;
+    bool uniform_L = true;
+    std::vector<NmpcClass> classes;
+    int* d_queue = nullptr;   // one counter per class
+    int64_t* d_pos_pi = nullptr;
+    double* d_phi = nullptr;
+    double* d_flops = nullptr;
+    int32_t* d_cnt = nullptr;
+    uint64_t* d_hash = nullptr;
+    double* d_stats = nullptr;
+    unsigned long long* d_hist = nullptr;
+    long long* d_totals = nullptr;
+    // PI reverse pass
+    int ckC = 0;
+    double* d_ck = nullptr;
+    double* d_tape = nullptr;
+    double* d_ivtape = nullptr;
+    double* d_gk = nullptr;
+    double* d_gsum = nullptr;
+    hipEvent_t ev[6] = {};
+    hipStream_t last = nullptr;
+    bool ran = false;
+    bool grad_ran = false;
+    size_t bytes = 0;
+    std::vector<void*> allocs;
+
+    template <class T>
+    int alloc(T** p, size_t n) {
+        *p = nullptr;
+        if (n == 0) return MC_CL_OK;
+        void* v = nullptr;
+        HIPCHK(hipMalloc(&v, n * sizeof(T)));
+        allocs.push_back(v);
+        bytes += n * sizeof(T);
+        *p = (T*)v;
+        return MC_CL_OK;
+    }
+    ~mc_cl_ctx() {
+        (void)hipSetDevice(device);
+        (void)hipDeviceSynchronize();
+        for (void* v : allocs) (void)hipFree(v);
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+static int validate(const mc_cl_params* p) {
+    if (!p) return MC_CL_EINVAL;
+    if (p->struct_size != sizeof(mc_cl_params) || p->abi_version != MC_CL_ABI_VERSION)
+        return MC_CL_EINVAL;
+    const double fin[] = {p->V, p->k0, p->EaR, p->beta, p->cAin, p->cBin, p->cTin, p->sigma[0],
+                          p->sigma[1], p->sigma[2], p->Rmeas, p->Ts, p->Qz, p->umin, p->umax,
+                          p->sqp_eps, p->ls_c1, p->ls_beta, p->kP, p->kI, p->kaw, p->pi_umin,
+                          p->pi_umax, p->P0, p->x0_rel_std, p->sp_step_rel, p->kin_lognorm_sigma,
+                          p->noise_scale};
+    for (double v : fin)
+        if (!is_finite(v)) return MC_CL_EINVAL;
+    if (!(p->V > 0) || !(p->Ts > 0) || !(p->beta != 0) || !(p->k0 >= 0) || !(p->EaR > 0))
+        return MC_CL_EINVAL;
+    if (p->Ns < 1 || p->Nc < 1 || p->L < 0 || p->n_samples < 1) return MC_CL_EINVAL;
+    if (p->N < 1 || p->N > MC_CL_NMAX || p->umin > p->umax || p->pi_umin > p->pi_umax)
+        return MC_CL_EINVAL;
+    if (p->Rmeas < 0 || p->P0 <= 0 || p->sigma[0] < 0 || p->sigma[1] < 0 || p->sigma[2] < 0)
+        return MC_CL_EINVAL;
+    if (p->n_sp < 1 || p->n_sp > MC_CL_SPMAX || p->sp_i[0] != 0) return MC_CL_EINVAL;
+    for (int j = 0; j < p->n_sp; ++j) {
+        if (!is_finite(p->sp_z[j]) || p->sp_z[j] <= p->cTin) return MC_CL_EINVAL;
+        if (j > 0 && p->sp_i[j] <= p->sp_i[j - 1]) return MC_CL_EINVAL;
+    }
+    if (p->sp_period < 0) return MC_CL_EINVAL;
+    if (p->sp_step_rel != 0.0 && (p->sp_step_lo < 0 || p->sp_step_hi < p->sp_step_lo))
+        return MC_CL_EINVAL;
+    if (p->n_horizon_choices < 0 || p->n_horizon_choices > 4) return MC_CL_EINVAL;
+    for (int j = 0; j < p->n_horizon_choices; ++j)
+        if (p->horizon_choices[j] < 1 || p->horizon_choices[j] > MC_CL_NMAX) return MC_CL_EINVAL;
+    if (p->L_lo < p->L_hi && p->L_lo < 0) return MC_CL_EINVAL;
+    if (p->sqp_max_iter < 0 || p->ls_max_bt < 0 || p->ipm_max_iter < 1) return MC_CL_EINVAL;
+    if (p->grad_mode != 0 && p->grad_mode != 1) return MC_CL_EINVAL;
+    if (p->x0_mode != 0 && p->x0_mode != 1) return MC_CL_EINVAL;
+    if (p->default_kind != 0 && p->default_kind != 1) return MC_CL_EINVAL;
+    if (!(p->ls_beta > 0 && p->ls_beta < 1) || !(p->ls_c1 > 0 && p->ls_c1 < 1)) return MC_CL_EINVAL;
+    if (p->kP == 0.0 || p->kI == 0.0) return MC_CL_EINVAL;
+    if (p->ckpt_interval < 0 || p->samples_per_wave < 0 || p->samples_per_wave > 64)
+        return MC_CL_EINVAL;
+    if (p->qp_solver != 0 && p->qp_solver != 1) return MC_CL_EINVAL;
+    if (p->sample_id_offset < 0 || p->sample_id_offset + p->n_samples > (int64_t)UINT32_MAX)
+        return MC_CL_EINVAL;
+    return MC_CL_OK;
+}
+
+static DevParams to_dev(const mc_cl_params& p) {
+    DevParams d{};
+    d.V = p.V; d.k0 = p.k0; d.EaR = p.EaR; d.beta = p.beta;
+    d.cAin = p.cAin; d.cBin = p.cBin; d.cTin = p.cTin;
+    for (int a = 0; a < 3; ++a) d.sig[a] = p.sigma[a];
+    d.Rmeas = p.Rmeas; d.Ts = p.Ts; d.Ns = p.Ns; d.L = p.L;
+    d.n_sp = p.n_sp; d.sp_period = p.sp_period;
+    for (int j = 0; j < kSpMax; ++j) { d.sp_i[j] = p.sp_i[j]; d.sp_z[j] = p.sp_z[j]; }
+    d.sp_step_rel = p.sp_step_rel; d.sp_step_lo = p.sp_step_lo; d.sp_step_hi = p.sp_step_hi;
+    d.N = p.N; d.Nc = p.Nc; d.Qz = p.Qz; d.umin = p.umin; d.umax = p.umax;
+    d.sqp_eps = p.sqp_eps; d.ls_c1 = p.ls_c1; d.ls_beta = p.ls_beta;
+    d.sqp_max_iter = p.sqp_max_iter; d.ls_max_bt = p.ls_max_bt; d.grad_mode = p.grad_mode;
+    d.ipm_max_iter = p.ipm_max_iter;
+    d.kP = p.kP; d.kI = p.kI; d.kaw = p.kaw; d.pi_umin = p.pi_umin; d.pi_umax = p.pi_umax;
+    d.P0 = p.P0; d.x0_rel_std = p.x0_rel_std; d.x0_mode = p.x0_mode;
+    d.kind_split = p.kind_split; d.default_kind = p.default_kind;
+    d.run_ekf_for_pi = p.run_ekf_for_pi;
+    d.seed = p.seed; d.noise_mod = p.noise_mod; d.n_samples = p.n_samples;
+    d.id_offset = p.sample_id_offset;
+    d.n_hc = p.n_horizon_choices;
+    for (int j = 0; j < 4; ++j) d.hc[j] = p.horizon_choices[j];
+    d.L_lo = p.L_lo; d.L_hi = p.L_hi; d.kin_sigma = p.kin_lognorm_sigma;
+    d.hess_warm = p.hess_warm; d.want_grad = p.want_grad; d.noise_scale = p.noise_scale;
+    d.ckpt_C = 0;
+    d.qp_solver = p.qp_solver;
+    return d;
+}
+
+static int nmax_class(int N) { return N <= 16 ? 16 : (N <= 32 ? 32 : 64); }
+
+// Samples per wavefront.  Per SQP iteration a wavefront spends a time in the
+// one-sample-per-lane phases that does not depend on how many of its lanes
+// carry samples (their serial RK4 chains are latency bound), plus one
+// cooperative QP per sample.  With rho = T_lane / T_qp (measured on MI355X:
+// about 46 at N = 60, scaling like 60 / N since the lane phases grow with N
+// and the QP's dependency chain with N^2), the campaign rate is proportional
+// to  resident_waves(spw) * spw / (rho + spw).  Pick the best of 8..64.
+static int choose_spw(int64_t count, int N, int slots_full) {
+    const double rho = 46.0 * 60.0 / (double)std::max(N, 1);
+    int best = 64;
+    double best_rate = -1.0;
+    for (int spw = 64; spw >= 8; spw >>= 1) {
+        const int64_t groups = (count + spw - 1) / spw;
+        const double resident = (double)std::min<int64_t>(groups, slots_full);
+        const double rate = resident * spw / (rho + spw);
+        if (rate > best_rate * 1.02) {
+            best_rate = rate;
+            best = spw;
+        }
+    }
+    return best;
+}
+
+extern "C" {
+
+uint32_t mc_cl_abi_version(void) { return MC_CL_ABI_VERSION; }
+
+const char* mc_cl_strerror(int status) {
+    switch (status) {
+        case MC_CL_OK: return "ok";
+        case MC_CL_EINVAL: return "invalid argument or parameter out of domain";
+        case MC_CL_EHIP: return g_hip_error.empty() ? "HIP runtime error" : g_hip_error.c_str();
+        case MC_CL_ENOMEM: return "device allocation failed";
+        case MC_CL_ESTATE: return "call out of order for this context";
+        case MC_CL_EUNSUPPORTED: return "unsupported request";
+        default: return "unknown status";
+    }
+}
+
+int mc_cl_create(const mc_cl_params* p, mc_cl_ctx** out) {
+    if (!out) return MC_CL_EINVAL;
+    int rc = validate(p);
+    if (rc != MC_CL_OK) return rc;
+    mc_cl_ctx* c = new (std::nothrow) mc_cl_ctx();
+    if (!c) return MC_CL_ENOMEM;
+    auto fail = [&](int code) {
+        delete c;
+        return code;
+    };
+    c->prm = *p;
+    c->dp = to_dev(*p);
+    c->S = p->n_samples;
+    if (hipGetDevice(&c->device) != hipSuccess) return fail(MC_CL_EHIP);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return fail(MC_CL_EHIP);
+    c->n_cu = prop.multiProcessorCount;
+    const int64_t S = c->S;
+
+    // plan: per-sample kind / N / L on the device
+    int32_t *d_kind, *d_N, *d_L;
+    if ((rc = c->alloc(&d_kind, S)) || (rc = c->alloc(&d_N, S)) || (rc = c->alloc(&d_L, S)))
+        return fail(rc);
+    hipLaunchKernelGGL(plan_kernel, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, 0, c->dp, S,
+                       d_kind, d_N, d_L);
+    std::vector<int32_t> kind(S), Nv(S), Lv(S);
+    if (hipMemcpy(kind.data(), d_kind, S * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(Nv.data(), d_N, S * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(Lv.data(), d_L, S * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(MC_CL_EHIP);
+    std::vector<int64_t> pi_pos;
+    std::vector<std::vector<int64_t>> cls_pos(3);
+    int Lmax = 0;
+    for (int64_t s = 0; s < S; ++s) {
+        Lmax = std::max(Lmax, Lv[s]);
+        if (Lv[s] != Lv[0]) c->uniform_L = false;
+        if (kind[s] == 1) pi_pos.push_back(s);
+        else cls_pos[nmax_class(Nv[s]) == 16 ? 0 : (nmax_class(Nv[s]) == 32 ? 1 : 2)].push_back(s);
+    }
+    c->n_pi = (int64_t)pi_pos.size();
+    if (c->n_pi) {
+        if ((rc = c->alloc(&c->d_pos_pi, c->n_pi))) return fail(rc);
+        if (hipMemcpy(c->d_pos_pi, pi_pos.data(), c->n_pi * 8, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(MC_CL_EHIP);
+    }
+    // NMPC classes: sorted by (N, L) descending so a wavefront's samples
+    // carry similar work
+    const int gmode = p->grad_mode;
+    const int nmaxs[3] = {16, 32, 64};
+    for (int k = 0; k < 3; ++k) {
+        auto& v = cls_pos[k];
+        if (v.empty()) continue;
+        std::stable_sort(v.begin(), v.end(), [&](int64_t a, int64_t b) {
+            if (Nv[a] != Nv[b]) return Nv[a] > Nv[b];
+            return Lv[a] > Lv[b];
+        });
+        NmpcClass nc;
+        nc.nmax = nmaxs[k];
+        nc.count = (int64_t)v.size();
+        c->n_nmpc += nc.count;
+        const int bpc = blocks_per_cu(nc.nmax, gmode);
+        const int slots_full = bpc * c->n_cu;
+        int nmax_in_class = 1;
+        for (int64_t q : v) nmax_in_class = std::max(nmax_in_class, Nv[q]);
+        nc.spw = p->samples_per_wave > 0 ? p->samples_per_wave
+                                         : choose_spw(nc.count, nmax_in_class, slots_full);
+        nc.groups = (int)((nc.count + nc.spw - 1) / nc.spw);
+        nc.slots = std::min(nc.groups, slots_full);
+        nc.tile_stride = (int64_t)V_COUNT * nc.nmax * 64;
+        nc.xs_stride = ((int64_t)nc.nmax * p->Nc * 4 + 1) * 64;
+        nc.w_stride = (int64_t)nc.spw * nc.nmax * nc.nmax;
+        if ((rc = c->alloc(&nc.d_pos, nc.count)) ||
+            (rc = c->alloc(&nc.d_tiles, (size_t)nc.slots * nc.tile_stride)) ||
+            (rc = c->alloc(&nc.d_xs, (size_t)nc.slots * nc.xs_stride)) ||
+            (rc = c->alloc(&nc.d_W, (size_t)nc.slots * nc.w_stride)))
+            return fail(rc);
+        if (hipMemcpy(nc.d_pos, v.data(), nc.count * 8, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(MC_CL_EHIP);
+        if (hipMemset(nc.d_W, 0, (size_t)nc.slots * nc.w_stride * 8) != hipSuccess)
+            return fail(MC_CL_EHIP);
+        c->classes.push_back(nc);
+    }
+    if ((rc = c->alloc(&c->d_queue, 4)) || (rc = c->alloc(&c->d_phi, S)) ||
+        (rc = c->alloc(&c->d_flops, S)) || (rc = c->alloc(&c->d_cnt, (size_t)C_NCNT * S)) ||
+        (rc = c->alloc(&c->d_hash, S)) || (rc = c->alloc(&c->d_stats, 8)) ||
+        (rc = c->alloc(&c->d_hist, 2 * MC_CL_NHIST)) || (rc = c->alloc(&c->d_totals, MC_CL_NCNT)))
+        return fail(rc);
+    if (p->want_grad && c->n_pi) {
+        c->ckC = p->ckpt_interval > 0 ? p->ckpt_interval : 50;
+        const int64_t nseg = (Lmax + c->ckC - 1) / c->ckC;
+        c->dp.ckpt_C = c->ckC;
+        if ((rc = c->alloc(&c->d_ck, (size_t)std::max<int64_t>(nseg, 1) * 4 * c->n_pi)) ||
+            (rc = c->alloc(&c->d_tape, (size_t)c->ckC * p->Ns * 6 * c->n_pi)) ||
+            (rc = c->alloc(&c->d_ivtape, (size_t)c->ckC * 5 * c->n_pi)) ||
+            (rc = c->alloc(&c->d_gk, (size_t)2 * c->n_pi)) || (rc = c->alloc(&c->d_gsum, 2)))
+            return fail(rc);
+    }
+    for (auto& e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) return fail(MC_CL_EHIP);
+    *out = c;
+    return MC_CL_OK;
+}
+
+int mc_cl_run(mc_cl_ctx* c, void* hip_stream, const mc_cl_outputs* o) {
+    if (!c) return MC_CL_EINVAL;
+    if (o && (o->traj_z || o->traj_u || o->traj_xhat) && !c->uniform_L) return MC_CL_ESTATE;
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    Outs out{c->d_phi, c->d_flops, c->d_cnt, c->d_hash,
+             o ? o->traj_z : nullptr, o ? o->traj_u : nullptr, o ? o->traj_xhat : nullptr, c->S};
+    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, c->d_queue, 4, 0);
+    hipLaunchKernelGGL(fill_u64, dim3((2 * MC_CL_NHIST + MC_CL_NCNT + 255) / 256), dim3(256), 0,
+                       st, c->d_hist, 2 * MC_CL_NHIST);
+    hipLaunchKernelGGL(fill_u64, dim3(1), dim3(64), 0, st, (unsigned long long*)c->d_totals,
+                       MC_CL_NCNT);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(c->ev[0], st));
+    for (size_t k = 0; k < c->classes.size(); ++k) {
+        const NmpcClass& nc = c->classes[k];
+        NmpcWork wk{nc.d_pos, nc.count, nc.spw, nc.groups, c->d_queue + k,
+                    nc.d_tiles, nc.d_xs, nc.d_W, nc.tile_stride, nc.xs_stride, nc.w_stride};
+        HIPCHK(dispatch_nmpc(nc.nmax, c->prm.grad_mode, c->dp, wk, out, nc.slots, st));
+    }
+    HIPCHK(hipEventRecord(c->ev[1], st));
+    if (c->n_pi) {
+        hipLaunchKernelGGL(pi_kernel, dim3((unsigned)((c->n_pi + 63) / 64)), dim3(64), 0, st, c->dp,
+                           c->d_pos_pi, c->n_pi, out, c->d_ck);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipEventRecord(c->ev[2], st));
+    hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(1024), 0, st, c->d_phi, c->d_cnt, c->S,
+                       c->d_flops, c->d_stats, c->d_hist, c->d_totals);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(c->ev[3], st));
+    if (o) {
+        if (o->phi) HIPCHK(hipMemcpyAsync(o->phi, c->d_phi, c->S * 8, hipMemcpyDeviceToDevice, st));
+        if (o->counters)
+            HIPCHK(hipMemcpyAsync(o->counters, c->d_cnt, (size_t)C_NCNT * c->S * 4,
+                                  hipMemcpyDeviceToDevice, st));
+        if (o->ashash)
+            HIPCHK(hipMemcpyAsync(o->ashash, c->d_hash, c->S * 8, hipMemcpyDeviceToDevice, st));
+    }
+    c->last = st;
+    c->ran = true;
+    return MC_CL_OK;
+}
+
+int mc_cl_costs(mc_cl_ctx* c, double* phi_host, mc_cl_stats* sto) {
+    if (!c) return MC_CL_EINVAL;
+    if (!c->ran) return MC_CL_ESTATE;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize(c->last));
+    if (phi_host) HIPCHK(hipMemcpy(phi_host, c->d_phi, c->S * 8, hipMemcpyDeviceToHost));
+    if (sto) {
+        double s8[8];
+        unsigned long long hist[2 * MC_CL_NHIST];
+        long long tot[MC_CL_NCNT];
+        HIPCHK(hipMemcpy(s8, c->d_stats, sizeof(s8), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(hist, c->d_hist, sizeof(hist), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(tot, c->d_totals, sizeof(tot), hipMemcpyDeviceToHost));
+        std::memset(sto, 0, sizeof(*sto));
+        for (int k = 0; k < 2; ++k) {
+            sto->count[k] = (int64_t)s8[k * 3 + 0];
+            sto->mean[k] = s8[k * 3 + 1];
+            sto->var[k] = s8[k * 3 + 2];
+            for (int b = 0; b < MC_CL_NHIST; ++b) sto->hist[k][b] = (int64_t)hist[k * MC_CL_NHIST + b];
+        }
+        for (int r = 0; r < MC_CL_NCNT; ++r) sto->totals[r] = tot[r];
+        sto->flops_algorithmic = s8[6] + s8[7];
+        sto->flops_by_kind[0] = s8[6];
+        sto->flops_by_kind[1] = s8[7];
+        sto->workspace_bytes = c->bytes;
+    }
+    return MC_CL_OK;
+}
+
+int mc_cl_grad(mc_cl_ctx* c, void* hip_stream, double g[2], double* per_sample) {
+    if (!c || !g) return MC_CL_EINVAL;
+    if (!c->ran || !c->prm.want_grad || c->n_pi == 0 || !c->d_ck) return MC_CL_ESTATE;
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIPCHK(hipEventRecord(c->ev[4], st));
+    hipLaunchKernelGGL(pi_reverse_kernel, dim3((unsigned)((c->n_pi + 63) / 64)), dim3(64), 0, st,
+                       c->dp, c->d_pos_pi, c->n_pi, c->d_ck, c->d_tape, c->d_ivtape, c->d_gk);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3(1), dim3(1024), 0, st, c->d_gk, c->n_pi, c->d_gsum);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(c->ev[5], st));
+    c->grad_ran = true;
+    double gs[2];
+    HIPCHK(hipMemcpyAsync(gs, c->d_gsum, sizeof(gs), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    // theta = (Kc, tau_i), kP = Kc, kI = Kc / tau_i
+    const double Kc = c->prm.kP, taui = c->prm.kP / c->prm.kI;
+    const double dkP = gs[0] / (double)c->n_pi, dkI = gs[1] / (double)c->n_pi;
+    g[0] = dkP + dkI / taui;
+    g[1] = dkI * (-Kc / (taui * taui));
+    if (per_sample) {
+        // per-sample (Kc, tau_i) derivatives at the sample columns; zero for NMPC
+        std::vector<double> gk(2 * c->n_pi), ps(2 * c->S, 0.0);
+        std::vector<int64_t> pos(c->n_pi);
+        HIPCHK(hipMemcpy(gk.data(), c->d_gk, gk.size() * 8, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(pos.data(), c->d_pos_pi, pos.size() * 8, hipMemcpyDeviceToHost));
+        for (int64_t t = 0; t < c->n_pi; ++t) {
+            ps[pos[t]] = gk[t] + gk[c->n_pi + t] / taui;
+            ps[c->S + pos[t]] = gk[c->n_pi + t] * (-Kc / (taui * taui));
+        }
+        HIPCHK(hipMemcpy(per_sample, ps.data(), ps.size() * 8, hipMemcpyHostToDevice));
+    }
+    return MC_CL_OK;
+}
+
+void mc_cl_destroy(mc_cl_ctx* c) { delete c; }
+
+int mc_cl_kernel_ms(mc_cl_ctx* c, float ms[4]) {
+    if (!c || !ms || !c->ran) return MC_CL_ESTATE;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipEventSynchronize(c->ev[3]));
+    HIPCHK(hipEventElapsedTime(&ms[0], c->ev[0], c->ev[1]));
+    HIPCHK(hipEventElapsedTime(&ms[1], c->ev[1], c->ev[2]));
+    HIPCHK(hipEventElapsedTime(&ms[2], c->ev[2], c->ev[3]));
+    ms[3] = 0.0f;
+    if (c->grad_ran) HIPCHK(hipEventElapsedTime(&ms[3], c->ev[4], c->ev[5]));
+    return MC_CL_OK;
+}
+
+int mc_cl_plan(mc_cl_ctx* c, int32_t* out, int max_classes) {
+    if (!c || !out) return MC_CL_EINVAL;
+    int n = 0;
+    for (const auto& k : c->classes) {
+        if (n >= max_classes) break;
+        out[n * 5 + 0] = k.nmax;
+        out[n * 5 + 1] = (int32_t)k.count;
+        out[n * 5 + 2] = k.spw;
+        out[n * 5 + 3] = k.groups;
+        out[n * 5 + 4] = k.slots;
+        ++n;
+    }
+    return n;
+}
+
+}  // extern "C"

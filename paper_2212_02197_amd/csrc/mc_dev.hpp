@@ -1,0 +1,403 @@
+// mc_dev.hpp -- device building blocks of the Monte Carlo closed-loop CSTR
+// (arXiv 2212.02197) for gfx950: counter-based noise, plant and model right-
+// hand sides, CD-EKF, PI law, RK4 single shooting with adjoint and forward-
+// sensitivity gradients.  One sample per lane; FP64 throughout.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mccl {
+
+constexpr double kMlMinPerLs = 60000.0;   // 1 L/s = 60000 mL/min
+constexpr int kSpMax = 8;
+constexpr int kTile = 64;                  // lanes per wavefront (CDNA)
+
+// Parameters as the kernels see them (passed by value as a kernel argument).
+struct DevParams {
+    double V, k0, EaR, beta, cAin, cBin, cTin;
+    double sig[3];
+    double Rmeas, Ts;
+    int Ns, L;
+    int n_sp, sp_period;
+    int sp_i[kSpMax];
+    double sp_z[kSpMax];
+    double sp_step_rel;
+    int sp_step_lo, sp_step_hi;
+    int N, Nc;
+    double Qz, umin, umax;
+    double sqp_eps, ls_c1, ls_beta;
+    int sqp_max_iter, ls_max_bt, grad_mode, ipm_max_iter;
+    double kP, kI, kaw, pi_umin, pi_umax;
+    double P0, x0_rel_std;
+    int x0_mode, kind_split, default_kind, run_ekf_for_pi;
+    uint64_t seed;
+    int64_t noise_mod, n_samples, id_offset;
+    int n_hc;
+    int hc[4];
+    int L_lo, L_hi;
+    double kin_sigma;
+    int hess_warm, want_grad;
+    double noise_scale;
+    int ckpt_C, qp_solver;
+};
+
+// Noise streams: the counter's last word.
+enum : uint32_t { kTagProcess = 0, kTagMeas = 1, kTagX0 = 2, kTagKin = 3, kTagScen = 4 };
+
+// ---------------------------------------------------------------- Philox ---
+// Philox4x32-10 (Salmon et al., SC'11): counter (block, step, id, tag),
+// key (seed lo, seed hi).
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo0 = 0xD2511F53u * c[0];
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2];
+        const uint32_t n0 = hi1 ^ c[1] ^ k0;
+        const uint32_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+struct Uniform2 { double u1, u2; };
+
+// Two 53-bit uniforms from one block: u1 in (0, 1], u2 in [0, 1).
+__device__ __forceinline__ Uniform2 philox_uniforms(uint64_t seed, uint32_t block, uint32_t step,
+                                                     uint32_t id, uint32_t tag) {
+    uint32_t c[4] = {block, step, id, tag};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint64_t m1 = ((((uint64_t)c[0]) << 32) | c[1]) >> 11;
+    const uint64_t m2 = ((((uint64_t)c[2]) << 32) | c[3]) >> 11;
+    Uniform2 r;
+    r.u1 = (double)(m1 + 1) * 0x1p-53;
+    r.u2 = (double)m2 * 0x1p-53;
+    return r;
+}
+
+// Box-Muller: xi0 = rho cos(2 pi u2), xi1 = rho sin(2 pi u2).
+__device__ __forceinline__ void normal_pair(uint64_t seed, uint32_t block, uint32_t step,
+                                            uint32_t id, uint32_t tag, double& xi0, double& xi1) {
+    const Uniform2 u = philox_uniforms(seed, block, step, id, tag);
+    const double rho = sqrt(-2.0 * log(u.u1));
+    double s, c;
+    sincos(6.283185307179586 * u.u2, &s, &c);
+    xi0 = rho * c;
+    xi1 = rho * s;
+}
+
+__device__ __forceinline__ double normal_first(uint64_t seed, uint32_t block, uint32_t step,
+                                               uint32_t id, uint32_t tag) {
+    const Uniform2 u = philox_uniforms(seed, block, step, id, tag);
+    return sqrt(-2.0 * log(u.u1)) * cos(6.283185307179586 * u.u2);
+}
+
+// -------------------------------------------------------------- the model ---
+// Three-state plant drift, eq. (CSTR): C_in F - c F + S r V, S = [-1,-2,beta].
+__device__ __forceinline__ void plant_f3(const DevParams& p, double k0, double EaR,
+                                         const double n[3], double F, double f[3]) {
+    const double iV = 1.0 / p.V;
+    const double cA = n[0] * iV, cB = n[1] * iV, cT = n[2] * iV;
+    const double rV = k0 * exp(-EaR / cT) * cA * cB * p.V;
+    f[0] = (p.cAin - cA) * F - rV;
+    f[1] = (p.cBin - cB) * F - 2.0 * rV;
+    f[2] = (p.cTin - cT) * F + p.beta * rV;
+}
+
+// One-state model x = n_T with the reaction-invariant closure; returns
+// f1 and (optionally) df1/dx, df1/dF.
+template <bool kDeriv>
+__device__ __forceinline__ double model_f1(const DevParams& p, double x, double F,
+                                           double& fx, double& fF) {
+    const double iV = 1.0 / p.V;
+    const double cT = x * iV;
+    const double dT = p.cTin - cT;
+    const double ib = 1.0 / p.beta;
+    const double cA = p.cAin + dT * ib;
+    const double cB = p.cBin + 2.0 * dT * ib;
+    const double icT = 1.0 / cT;
+    const double k = p.k0 * exp(-p.EaR * icT);
+    const double r = k * cA * cB;
+    if (kDeriv) {
+        const double dr = r * (p.EaR * icT * icT) - k * ib * (cB + 2.0 * cA);
+        fx = -F * iV + p.beta * dr;
+        fF = dT;
+    }
+    return dT * F + p.beta * r * p.V;
+}
+
+__device__ __forceinline__ double model_f1(const DevParams& p, double x, double F) {
+    double a, b;
+    return model_f1<false>(p, x, F, a, b);
+}
+
+// Euler-Maruyama sub-step n += h f3 + F sigma sqrt(h) xi.
+__device__ __forceinline__ void em_step(const DevParams& p, double k0, double EaR, double n[3],
+                                        double F, double h, double sqh, const double xi[3]) {
+    double f[3];
+    plant_f3(p, k0, EaR, n, F, f);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) n[a] = n[a] + h * f[a] + F * p.sig[a] * sqh * xi[a];
+}
+
+// The three process-noise normals of sub-step `step` (blocks 0 and 1).
+__device__ __forceinline__ void process_noise(const DevParams& p, uint32_t step, uint32_t id,
+                                              double xi[3]) {
+    normal_pair(p.seed, 0, step, id, kTagProcess, xi[0], xi[1]);
+    xi[2] = normal_first(p.seed, 1, step, id, kTagProcess);
+    const double s = p.noise_scale;
+    xi[0] *= s; xi[1] *= s; xi[2] *= s;
+}
+
+// ------------------------------------------------------------- setpoint ---
+__device__ __forceinline__ double setpoint(const DevParams& p, int i, int istep, double sign) {
+    const int ii = p.sp_period > 0 ? i % p.sp_period : i;
+    double z = p.sp_z[0];
+    for (int j = 1; j < p.n_sp; ++j)
+        if (ii >= p.sp_i[j]) z = p.sp_z[j];
+    if (p.sp_step_rel != 0.0 && i >= istep) z = z * (1.0 + sign * p.sp_step_rel);
+    return z;
+}
+
+// ---------------------------------------------------------------- CD-EKF ---
+// Prediction over one sampling interval, RK4 with Nc steps on (x, P).
+__device__ __forceinline__ void ekf_predict(const DevParams& p, double& x, double& P, double F) {
+    const double h = p.Ts / (double)p.Nc;
+    const double q = (F * p.sig[2]) * (F * p.sig[2]);
+    double X = x, PP = P;
+    #pragma unroll 1
+    for (int c = 0; c < p.Nc; ++c) {
+        double a1, a2, a3, a4, b;
+        const double k1x = model_f1<true>(p, X, F, a1, b);
+        const double k1P = 2.0 * a1 * PP + q;
+        const double k2x = model_f1<true>(p, X + 0.5 * h * k1x, F, a2, b);
+        const double k2P = 2.0 * a2 * (PP + 0.5 * h * k1P) + q;
+        const double k3x = model_f1<true>(p, X + 0.5 * h * k2x, F, a3, b);
+        const double k3P = 2.0 * a3 * (PP + 0.5 * h * k2P) + q;
+        const double k4x = model_f1<true>(p, X + h * k3x, F, a4, b);
+        const double k4P = 2.0 * a4 * (PP + h * k3P) + q;
+        X = X + h / 6.0 * (k1x + 2.0 * k2x + 2.0 * k3x + k4x);
+        PP = PP + h / 6.0 * (k1P + 2.0 * k2P + 2.0 * k3P + k4P);
+    }
+    x = X;
+    P = PP;
+}
+
+// Filtering with the Joseph-form covariance, C = 1/V.
+__device__ __forceinline__ void ekf_update(const DevParams& p, double& x, double& P, double y) {
+    const double C = 1.0 / p.V;
+    const double e = y - x * C;
+    const double Re = p.Rmeas + C * P * C;
+    const double K = P * C / Re;
+    const double IKC = 1.0 - K * C;
+    x = x + K * e;
+    P = IKC * P * IKC + K * p.Rmeas * K;
+}
+
+// --------------------------------------------------------- sample set-up ---
+struct Setup {
+    uint32_t nid;       // noise id
+    int kind, N, L, istep;
+    double sign, k0, EaR;
+    double n0[3], xhat0, ubar;  // ubar in L/s
+};
+
+__device__ __forceinline__ Setup sample_setup(const DevParams& p, int64_t sid) {
+    Setup s;
+    const int64_t nid = p.noise_mod > 0 ? sid % p.noise_mod : sid;
+    s.nid = (uint32_t)nid;
+    s.kind = p.kind_split >= 0 ? (sid < p.kind_split ? 0 : 1) : p.default_kind;
+    s.N = p.N;
+    s.L = p.L;
+    if (p.n_hc > 0) {
+        const double u = philox_uniforms(p.seed, 0, 0, s.nid, kTagScen).u2;
+        s.N = p.hc[(int)floor(u * p.n_hc)];
+    }
+    if (p.L_lo < p.L_hi) {
+        const double u = philox_uniforms(p.seed, 1, 0, s.nid, kTagScen).u2;
+        s.L = p.L_lo + (int)floor(u * (double)(p.L_hi - p.L_lo + 1));
+    }
+    s.istep = 0;
+    s.sign = 0.0;
+    if (p.sp_step_rel != 0.0) {
+        const double u = philox_uniforms(p.seed, 2, 0, s.nid, kTagScen).u2;
+        s.istep = p.sp_step_lo + (int)floor(u * (double)(p.sp_step_hi - p.sp_step_lo + 1));
+        const double v = philox_uniforms(p.seed, 3, 0, s.nid, kTagScen).u2;
+        s.sign = v < 0.5 ? 1.0 : -1.0;
+    }
+    s.k0 = p.k0;
+    s.EaR = p.EaR;
+    if (p.kin_sigma > 0.0) {
+        double a, b;
+        normal_pair(p.seed, 0, 0, s.nid, kTagKin, a, b);
+        s.k0 = p.k0 * exp(p.kin_sigma * a);
+        s.EaR = p.EaR * exp(p.kin_sigma * b);
+    }
+    // steady state of the one-state model at zbar(0)
+    const double T = setpoint(p, 0, s.istep, s.sign);
+    const double cA = p.cAin + (p.cTin - T) / p.beta;
+    const double cB = p.cBin + 2.0 * (p.cTin - T) / p.beta;
+    const double r = p.k0 * exp(-p.EaR / T) * cA * cB;
+    s.ubar = p.beta * r * p.V / (T - p.cTin);
+    if (p.x0_mode == 0) {
+        s.n0[0] = p.cAin * p.V;
+        s.n0[1] = p.cBin * p.V;
+        s.n0[2] = p.cTin * p.V;
+        s.xhat0 = p.cTin * p.V;
+    } else {
+        double a, b;
+        normal_pair(p.seed, 0, 0, s.nid, kTagX0, a, b);
+        const double c = normal_first(p.seed, 1, 0, s.nid, kTagX0);
+        s.n0[0] = cA * p.V * (1.0 + p.x0_rel_std * a);
+        s.n0[1] = cB * p.V * (1.0 + p.x0_rel_std * b);
+        s.n0[2] = T * p.V * (1.0 + p.x0_rel_std * c);
+        s.xhat0 = T * p.V;
+    }
+    return s;
+}
+
+// ---------------------------------------------------- single shooting ---
+// Lane-tiled vectors: element k of the lane's sample at t[k * kTile].
+// Objective of the OCP at u + alpha d (d ignored when use_d is false).  The
+// trajectory goes to xs: for RK4 step m (m = k Nc + c) its start state and
+// first three stage slopes at xs[(4 m + 0..3) kTile], the final state at
+// xs[4 N Nc kTile]; the gradient sweeps then evaluate the four stage
+// derivatives of a step independently of each other.
+__device__ __forceinline__ double ocp_shoot(const DevParams& p, int N, double x0, int i0,
+                                            int istep, double sign, const double* u,
+                                            const double* d, double alpha, bool use_d,
+                                            double* xs) {
+    const double h = p.Ts / (double)p.Nc;
+    const double iV = 1.0 / p.V;
+    double x = x0, phi = 0.0;
+    int m = 0;
+#pragma unroll 1
+    for (int k = 0; k < N; ++k) {
+        double uk = u[k * kTile];
+        if (use_d) uk = uk + alpha * d[k * kTile];
+        const double F = uk / kMlMinPerLs;
+#pragma unroll 1
+        for (int c = 0; c < p.Nc; ++c, ++m) {
+            const double k1 = model_f1(p, x, F);
+            const double k2 = model_f1(p, x + 0.5 * h * k1, F);
+            const double k3 = model_f1(p, x + 0.5 * h * k2, F);
+            const double k4 = model_f1(p, x + h * k3, F);
+            xs[(4 * m + 0) * kTile] = x;
+            xs[(4 * m + 1) * kTile] = k1;
+            xs[(4 * m + 2) * kTile] = k2;
+            xs[(4 * m + 3) * kTile] = k3;
+            x = x + h / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4);
+        }
+        const double ez = x * iV - setpoint(p, i0 + 1 + k, istep, sign);
+        phi += p.Qz * ez * ez * p.Ts;
+    }
+    xs[(4 * m) * kTile] = x;
+    return phi;
+}
+
+// Stage derivatives of RK4 step m from the stored trajectory:
+// a_s = df1/dx and b_s = df1/dF at the four stage arguments.
+__device__ __forceinline__ void rk4_stage_derivs(const DevParams& p, const double* xs, int m,
+                                                 double F, double h, double (&a)[4],
+                                                 double (&b)[4]) {
+    const double x = xs[(4 * m + 0) * kTile];
+    const double k1 = xs[(4 * m + 1) * kTile];
+    const double k2 = xs[(4 * m + 2) * kTile];
+    const double k3 = xs[(4 * m + 3) * kTile];
+    const double X[4] = {x, x + 0.5 * h * k1, x + 0.5 * h * k2, x + h * k3};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) (void)model_f1<true>(p, X[s], F, a[s], b[s]);
+}
+
+// Discrete adjoint of the RK4 shooting: lambda runs back through every step.
+// Writes g[k] = dphi/du_k (mL/min) and, when y is given, y[k] = new - old
+// g[k] (the BFGS difference of the SQP).
+__device__ __forceinline__ void ocp_grad_adjoint(const DevParams& p, int N, int i0, int istep,
+                                                 double sign, const double* u, const double* xs,
+                                                 double* g, double* y) {
+    const double h = p.Ts / (double)p.Nc;
+    const double iV = 1.0 / p.V;
+    double lam = 0.0;
+#pragma unroll 1
+    for (int k = N - 1; k >= 0; --k) {
+        const double F = u[k * kTile] / kMlMinPerLs;
+        double Fbar = 0.0;
+        {
+            const double xk1 = xs[(4 * (k + 1) * p.Nc) * kTile];
+            const double ez = xk1 * iV - setpoint(p, i0 + 1 + k, istep, sign);
+            lam += p.Qz * 2.0 * ez * iV * p.Ts;
+        }
+#pragma unroll 1
+        for (int c = p.Nc - 1; c >= 0; --c) {
+            double a[4], b[4];
+            rk4_stage_derivs(p, xs, k * p.Nc + c, F, h, a, b);
+            double xb = lam;
+            double kb1 = lam * h / 6.0, kb2 = lam * h / 3.0, kb3 = lam * h / 3.0;
+            const double kb4 = lam * h / 6.0;
+            xb += kb4 * a[3];  kb3 += kb4 * a[3] * h;        Fbar += kb4 * b[3];
+            xb += kb3 * a[2];  kb2 += kb3 * a[2] * 0.5 * h;  Fbar += kb3 * b[2];
+            xb += kb2 * a[1];  kb1 += kb2 * a[1] * 0.5 * h;  Fbar += kb2 * b[1];
+            xb += kb1 * a[0];                                Fbar += kb1 * b[0];
+            lam = xb;
+        }
+        const double gk = Fbar / kMlMinPerLs;
+        if (y) {
+            y[k * kTile] = gk - g[k * kTile];
+        }
+        g[k * kTile] = gk;
+    }
+}
+
+// Forward sensitivities: the tangent-linear RK4 carries dx/du_j for all
+// j <= k through each step (NMAX register slots, unrolled), with the stage
+// derivatives from the stored trajectory; dphi/du_j accumulates in the lane
+// tile `acc` (element j at acc[j * kTile]).
+template <int NMAX>
+__device__ __forceinline__ void ocp_grad_fwd(const DevParams& p, int N, int i0, int istep,
+                                             double sign, const double* u, const double* xs,
+                                             double* g, double* y, double* acc) {
+    const double h = p.Ts / (double)p.Nc;
+    const double iV = 1.0 / p.V;
+    const double dF = 1.0 / kMlMinPerLs;
+    double S[NMAX];
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) S[j] = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < N; ++j) acc[j * kTile] = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < N; ++k) {
+        const double F = u[k * kTile] / kMlMinPerLs;
+#pragma unroll 1
+        for (int c = 0; c < p.Nc; ++c) {
+            double a[4], b[4];
+            rk4_stage_derivs(p, xs, k * p.Nc + c, F, h, a, b);
+#pragma unroll
+            for (int j = 0; j < NMAX; ++j) {
+                if (j <= k) {
+                    const double src = (j == k) ? dF : 0.0;
+                    const double d1 = a[0] * S[j] + b[0] * src;
+                    const double d2 = a[1] * (S[j] + 0.5 * h * d1) + b[1] * src;
+                    const double d3 = a[2] * (S[j] + 0.5 * h * d2) + b[2] * src;
+                    const double d4 = a[3] * (S[j] + h * d3) + b[3] * src;
+                    S[j] = S[j] + h / 6.0 * (d1 + 2.0 * d2 + 2.0 * d3 + d4);
+                }
+            }
+        }
+        const double x = xs[(4 * (k + 1) * p.Nc) * kTile];
+        const double ez = x * iV - setpoint(p, i0 + 1 + k, istep, sign);
+        const double dphidx = p.Qz * 2.0 * ez * iV * p.Ts;
+#pragma unroll
+        for (int j = 0; j < NMAX; ++j)
+            if (j <= k) acc[j * kTile] += dphidx * S[j];
+    }
+#pragma unroll 1
+    for (int j = 0; j < N; ++j) {
+        const double gj = acc[j * kTile];
+        if (y) y[j * kTile] = gj - g[j * kTile];
+        g[j * kTile] = gj;
+    }
+}
+
+}  // namespace mccl

@@ -1,0 +1,670 @@
+// mc_kernels.hpp -- closed-loop kernels of the Monte Carlo CSTR campaign
+// (arXiv 2212.02197) for gfx950.
+//
+//  * pi_kernel: one sample per lane, the whole closed loop in registers.
+//  * nmpc_kernel: persistent; each 64-lane wavefront pulls groups of `spw`
+//    samples from a device work queue and runs their closed loops.  Scalar
+//    serial work (plant, estimator, RK4 shooting, gradient, line search, KKT
+//    test) runs one sample per lane; the dense QP and BFGS steps of the
+//    samples still iterating run on the whole wavefront, one sample at a
+//    time (ballot over the active lanes).
+//  * pi_reverse_kernel: reverse pass of the PI closed loop from plant-state
+//    checkpoints for dPhi/d(Kc, tau_i).
+//  * stats kernels: deterministic fixed-order reductions of Phi.
+#pragma once
+#include "mc_coop.hpp"
+#include "mc_dev.hpp"
+
+#ifndef MC_NMPC_WAVES_PER_EU
+#define MC_NMPC_WAVES_PER_EU 1   // wavefronts per SIMD the NMPC kernel is built for
+#endif
+
+namespace mccl {
+
+// Counter rows (match MC_CL_CNT_* of the C-ABI header).
+enum : int {
+    C_KIND = 0, C_N, C_L, C_OCP, C_OCP_FAIL, C_SQP, C_IPM, C_LS, C_LSCAP, C_SKIP, C_RESET,
+    C_IPMCAP, C_NONFIN, C_GRAD, C_AS, C_NCNT
+};
+
+struct Outs {
+    double* phi;       // [S]
+    double* flops;     // [S] algorithmic FP64 work of the sample
+    int32_t* cnt;      // [C_NCNT][S]
+    uint64_t* hash;    // [S]
+    double* tz;        // [L+1][S] or null
+    double* tu;        // [L][S] or null
+    double* tx;        // [L][S] or null
+    int64_t S;
+};
+
+// Lane-tiled per-sample vectors of the SQP (element k of lane l's sample at
+// base[(v * NMAX + k) * 64 + l]).
+enum : int { V_U = 0, V_G, V_D, V_PIL, V_PIU, V_NL, V_NU, V_S, V_Y, V_COUNT };
+
+struct NmpcWork {
+    const int64_t* pos;  // sample positions, grouped by spw
+    int64_t n_pos;
+    int spw;
+    int n_groups;
+    int* queue;
+    double* tiles;       // per slot: V_COUNT * NMAX * 64
+    double* xs;          // per slot: (4 NMAX Nc + 1) * 64 (states and stage slopes)
+    double* W;           // per slot: spw * NMAX * NMAX
+    int64_t tile_stride, xs_stride, w_stride;
+};
+
+__device__ __forceinline__ uint64_t fnv1a_step(uint64_t h, uint32_t i, uint64_t mask) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { h ^= (uint64_t)((i >> (8 * j)) & 0xffu); h *= 1099511628211ull; }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) { h ^= (mask >> (8 * j)) & 0xffull; h *= 1099511628211ull; }
+    return h;
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Algorithmic FP64 work of one sample from its counters (each +, -, *, /,
+// sqrt, exp, log, sin, cos counts 1; an FMA counts 2; Philox is integer):
+//   cost term 3, measurement 8, EM sub-step with its noise 52, PI law 10,
+//   EKF interval 142 Nc + 12, shooting 73 N Nc + 9 N,
+//   adjoint gradient 142 N Nc + 7 N,
+//   forward-sensitivity gradient 117 N Nc + 13 Nc N (N+1) + N (N+1) + 6 N,
+//   interior-point iteration N^3/3 + 7 N^2 + 60 N,
+//   active-set iteration N^3/3 + 6 N^2 + 10 N,
+//   BFGS 2 N^2 + 9 N per attempt + 6 N^2 per applied update,
+//   SQP bookkeeping 16 N per iteration.
+__device__ __forceinline__ double sample_flops(const DevParams& p, int kind, int N, int L,
+                                               const int (&c)[C_NCNT], int gmode) {
+    const double Ns = p.Ns, Nc = p.Nc, n = N, l = L;
+    double fl = 3.0 * (l + 1.0) + l * (8.0 + 52.0 * Ns);
+    if (kind == 0 || p.run_ekf_for_pi) fl += l * (142.0 * Nc + 12.0);
+    if (kind == 1) return fl + 10.0 * l;
+    const double shoot = 73.0 * n * Nc + 9.0 * n;
+    const double grad = gmode == 1 ? 142.0 * n * Nc + 7.0 * n
+                                   : 117.0 * n * Nc + 13.0 * Nc * n * (n + 1.0) + n * (n + 1.0) + 6.0 * n;
+    const double ipm = n * n * n / 3.0 + 7.0 * n * n + 60.0 * n;
+    const double asi = n * n * n / 3.0 + 6.0 * n * n + 10.0 * n;
+    fl += (double)c[C_LS] * shoot + (double)c[C_GRAD] * grad + (double)c[C_IPM] * ipm +
+          (double)c[C_AS] * asi;
+    fl += (double)c[C_SQP] * (2.0 * n * n + 9.0 * n + 16.0 * n) + (double)(c[C_SQP] - c[C_SKIP]) * 6.0 * n * n;
+    return fl;
+}
+
+// One SQP solve (SQP section, single shooting) for every lane with `live`;
+// returns per lane whether it converged.  u (V_U) holds the warm start on
+// entry and the last iterate on return.
+template <int NMAX, int GMODE>
+__device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, int i, const Setup& su,
+                          double xhat, int lane, double* TB, double* XS, double* Wslot,
+                          double* Wl, double* lds, int (&cnt)[C_NCNT]) {
+    double* const U = TB + (V_U * NMAX) * 64 + lane;
+    double* const G = TB + (V_G * NMAX) * 64 + lane;
+    double* const Dv = TB + (V_D * NMAX) * 64 + lane;
+    double* const PIL = TB + (V_PIL * NMAX) * 64 + lane;
+    double* const PIU = TB + (V_PIU * NMAX) * 64 + lane;
+    double* const NLv = TB + (V_NL * NMAX) * 64 + lane;
+    double* const NUv = TB + (V_NU * NMAX) * 64 + lane;
+    double* const Sv = TB + (V_S * NMAX) * 64 + lane;
+    double* const Yv = TB + (V_Y * NMAX) * 64 + lane;
+    double* const Xs = XS + lane;
+    static constexpr double smax = 100.0;
+
+    double f = 0.0;
+    if (live) {
+        #pragma unroll 1
+        for (int k = 0; k < N; ++k) {
+            double v = U[k * 64];
+            if (v < p.umin) v = p.umin;
+            if (v > p.umax) v = p.umax;
+            U[k * 64] = v;
+            PIL[k * 64] = 0.0;
+            PIU[k * 64] = 0.0;
+        }
+    }
+    // W = I for the first OCP (and every OCP without the warm start)
+    {
+        uint64_t m = __ballot(live && (i == 0 || !p.hess_warm));
+        while (m) {
+            const int s = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const int Ns_ = __builtin_amdgcn_readlane(N, s);
+            coop_identity<NMAX>(nullptr, Wslot + (int64_t)s * NMAX * NMAX, Ns_, lane);
+        }
+    }
+    if (live) {
+        f = ocp_shoot(p, N, xhat, i, su.istep, su.sign, U, Dv, 0.0, false, Xs);
+        cnt[C_LS]++;
+        if (GMODE == 1) ocp_grad_adjoint(p, N, i, su.istep, su.sign, U, Xs, G, nullptr);
+        else ocp_grad_fwd<NMAX>(p, N, i, su.istep, su.sign, U, Xs, G, nullptr, Dv);
+        cnt[C_GRAD]++;
+    }
+    bool active = live, pending = false, converged = false;
+    int l = 0;
+    for (;;) {
+        // scaled KKT test, eq. (convergence), on the lanes still iterating
+        if (active) {
+            double s1 = 0.0;
+            #pragma unroll 1
+            for (int k = 0; k < N; ++k) s1 += fabs(PIL[k * 64]) + fabs(PIU[k * 64]);
+            const double sd = (s1 / (2.0 * N) > smax ? s1 / (2.0 * N) : smax) / smax;
+            double kkt = 0.0;
+            bool bad = false;
+            #pragma unroll 1
+            for (int k = 0; k < N; ++k) {
+                const double t = fabs(G[k * 64] - PIL[k * 64] + PIU[k * 64]) / sd;
+                bad |= (t != t);
+                kkt = t > kkt ? t : kkt;
+            }
+            if (!bad && kkt <= p.sqp_eps) { converged = true; active = false; }
+            else if (l == p.sqp_max_iter) { active = false; }
+        }
+        // wavefront-cooperative phase: pending BFGS updates, then QPs
+        const uint64_t mp = __ballot(pending);
+        const uint64_t ma = __ballot(active);
+        uint64_t m = mp | ma;
+        while (m) {
+            const int s = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const int Ns_ = __builtin_amdgcn_readlane(N, s);
+            double* Ws = Wslot + (int64_t)s * NMAX * NMAX;
+            const bool in = lane < Ns_;
+            coop_stage<NMAX>(Ws, Wl, lane);
+            if ((mp >> s) & 1ull) {
+                const double si = in ? TB[(V_S * NMAX + lane) * 64 + s] : 0.0;
+                const double yi = in ? TB[(V_Y * NMAX + lane) * 64 + s] : 0.0;
+                const int upd = coop_bfgs<NMAX>(Wl, Ws, Ns_, lane, si, yi);
+                if (lane == s && !upd) cnt[C_SKIP]++;
+            }
+            if ((ma >> s) & 1ull) {
+                const double gi = in ? TB[(V_G * NMAX + lane) * 64 + s] : 0.0;
+                const double ui = in ? TB[(V_U * NMAX + lane) * 64 + s] : 0.0;
+                const double li = in ? TB[(V_PIL * NMAX + lane) * 64 + s] -
+                                           TB[(V_PIU * NMAX + lane) * 64 + s]
+                                     : 0.0;
+                double d = 0.0, nl = 0.0, nu = 0.0, Dg = 1.0;
+                QPResult r{0, 0};
+                int its = 0, ases = 0;
+                // a non-positive pivot or diagonal (W not positive definite):
+                // W <- I, solve again
+                for (int attempt = 0; attempt < 2; ++attempt) {
+                    if (attempt == 1) {
+                        if (lane == s) cnt[C_RESET]++;
+                        coop_identity<NMAX>(Wl, Ws, Ns_, lane);
+                    }
+                    if (!coop_scale<NMAX>(Wl, Ns_, lane, Dg)) {
+                        r.status = -1;
+                        continue;
+                    }
+                    r.status = 2;
+                    if (p.qp_solver == 1) {
+                        r = coop_box_qp_as<NMAX>(Wl, Ns_, lane, Dg, gi, ui, li, p.umin, p.umax, 8,
+                                                 d, nl, nu);
+                        ases += r.iters;
+                    }
+                    if (r.status == 2) {
+                        r = coop_box_qp<NMAX>(Wl, Ns_, lane, Dg, gi, ui, p.umin, p.umax,
+                                              p.ipm_max_iter, d, nl, nu);
+                        its += r.iters;
+                    }
+                    if (r.status != -1) break;
+                }
+                if (lane == s) {
+                    cnt[C_IPM] += its;
+                    cnt[C_AS] += ases;
+                    cnt[C_SQP]++;
+                    if (r.status == 1) cnt[C_IPMCAP]++;
+                }
+                if (in) {
+                    TB[(V_D * NMAX + lane) * 64 + s] = d;
+                    TB[(V_NL * NMAX + lane) * 64 + s] = nl;
+                    TB[(V_NU * NMAX + lane) * 64 + s] = nu;
+                }
+                __syncthreads();
+            }
+        }
+        pending = false;
+        if (ma == 0) break;
+        // backtracking line search, eq. (Armijo), one sample per lane
+        double D = 0.0, alpha = 1.0;
+        if (active)
+            #pragma unroll 1
+            for (int k = 0; k < N; ++k) D += G[k * 64] * Dv[k * 64];
+        bool searching = active;
+        int bt = 0;
+        while (__ballot(searching)) {
+            if (searching) {
+                const double ft = ocp_shoot(p, N, xhat, i, su.istep, su.sign, U, Dv, alpha, true, Xs);
+                cnt[C_LS]++;
+                bool accept = false;
+                if (bt == 0 && -D <= 64.0 * DBL_EPSILON * (1.0 + fabs(f))) accept = true;
+                else if (ft <= f + p.ls_c1 * alpha * D) accept = true;
+                else if (bt == p.ls_max_bt) { cnt[C_LSCAP]++; accept = true; }
+                if (accept) { searching = false; f = ft; }
+                else { alpha = p.ls_beta * alpha; ++bt; }
+            }
+        }
+        if (active) {
+            #pragma unroll 1
+            for (int k = 0; k < N; ++k) {
+                const double uo = U[k * 64];
+                const double un = uo + alpha * Dv[k * 64];
+                Sv[k * 64] = un - uo;
+                U[k * 64] = un;
+                PIL[k * 64] = PIL[k * 64] + alpha * (NLv[k * 64] - PIL[k * 64]);
+                PIU[k * 64] = PIU[k * 64] + alpha * (NUv[k * 64] - PIU[k * 64]);
+            }
+            if (GMODE == 1) ocp_grad_adjoint(p, N, i, su.istep, su.sign, U, Xs, G, Yv);
+            else ocp_grad_fwd<NMAX>(p, N, i, su.istep, su.sign, U, Xs, G, Yv, Dv);
+            cnt[C_GRAD]++;
+            pending = true;
+            ++l;
+        }
+    }
+    return converged;
+}
+
+template <int NMAX, int GMODE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVES_PER_EU))) void nmpc_kernel(DevParams p, NmpcWork wk, Outs out) {
+    __shared__ double lds[5 * 64];
+    __shared__ __attribute__((aligned(16))) double Wl[NMAX * NMAX];   // staged W of one sample
+    const int lane = threadIdx.x;
+    double* const TB = wk.tiles + (int64_t)blockIdx.x * wk.tile_stride;
+    double* const XS = wk.xs + (int64_t)blockIdx.x * wk.xs_stride;
+    double* const Wslot = wk.W + (int64_t)blockIdx.x * wk.w_stride;
+    double* const U = TB + (V_U * NMAX) * 64 + lane;
+    const double sqrtR = sqrt(p.Rmeas);
+    const double h = p.Ts / (double)p.Ns;
+    const double sqh = sqrt(h);
+
+    for (;;) {
+        int grp = 0;
+        if (lane == 0) grp = atomicAdd(wk.queue, 1);
+        grp = __shfl(grp, 0, 64);
+        if (grp >= wk.n_groups) break;
+        const int64_t idx = (int64_t)grp * wk.spw + lane;
+        const bool has = lane < wk.spw && idx < wk.n_pos;
+        const int64_t pos = has ? wk.pos[idx] : 0;
+        Setup su = sample_setup(p, p.id_offset + pos);
+        const int N = has ? su.N : 1;
+        const int L = has ? su.L : -1;
+        int cnt[C_NCNT];
+#pragma unroll
+        for (int c = 0; c < C_NCNT; ++c) cnt[c] = 0;
+        double n[3] = {su.n0[0], su.n0[1], su.n0[2]};
+        double xhat = su.xhat0, P = p.P0, Fprev = su.ubar, phiacc = 0.0;
+        uint64_t hsh = 14695981039346656037ull;
+        if (has)
+            #pragma unroll 1
+            for (int k = 0; k < N; ++k) U[k * 64] = su.ubar * kMlMinPerLs;
+        const int Lmax = wave_max_i(L);
+        for (int i = 0; i <= Lmax; ++i) {
+            const bool live = has && i <= L;
+            const bool step = live && i < L;
+            double z = 0.0;
+            if (live) {
+                z = n[2] / p.V;
+                const double zb = setpoint(p, i, su.istep, su.sign);
+                phiacc += (z - zb) * (z - zb);
+                if (out.tz) out.tz[(int64_t)i * out.S + pos] = z;
+            }
+            if (step) {
+                const double y = z + p.noise_scale * sqrtR *
+                                         normal_first(p.seed, 0, (uint32_t)i, su.nid, kTagMeas);
+                ekf_predict(p, xhat, P, Fprev);
+                ekf_update(p, xhat, P, y);
+                if (out.tx) out.tx[(int64_t)i * out.S + pos] = xhat;
+                if (!isfinite(xhat) || !isfinite(P)) cnt[C_NONFIN] = 1;
+            }
+            const bool conv = sqp_group<NMAX, GMODE>(p, step, N, i, su, xhat, lane, TB, XS, Wslot,
+                                                     Wl, lds, cnt);
+            if (p.hess_warm) {
+                uint64_t m = __ballot(step);
+                while (m) {
+                    const int s = __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1;
+                    const int Ns_ = __builtin_amdgcn_readlane(N, s);
+                    double* Ws = Wslot + (int64_t)s * NMAX * NMAX;
+                    coop_stage<NMAX>(Ws, Wl, lane);
+                    coop_shift<NMAX>(Wl, Ws, Ns_, lane);
+                }
+            }
+            if (step) {
+                cnt[C_OCP]++;
+                if (!conv) cnt[C_OCP_FAIL]++;
+                uint64_t mask = 0;
+                #pragma unroll 1
+                for (int k = 0; k < N; ++k) {
+                    const double v = U[k * 64];
+                    if (v <= p.umin + 1e-6 || v >= p.umax - 1e-6) mask |= (1ull << k);
+                }
+                hsh = fnv1a_step(hsh, (uint32_t)i, mask);
+                const double F = U[0] / kMlMinPerLs;
+                #pragma unroll 1
+                for (int k = 0; k + 1 < N; ++k) U[k * 64] = U[(k + 1) * 64];
+                if (out.tu) out.tu[(int64_t)i * out.S + pos] = F;
+                #pragma unroll 1
+                for (int j = 0; j < p.Ns; ++j) {
+                    double xi[3];
+                    process_noise(p, (uint32_t)(i * p.Ns + j), su.nid, xi);
+                    em_step(p, su.k0, su.EaR, n, F, h, sqh, xi);
+                }
+                Fprev = F;
+            }
+        }
+        if (has) {
+            if (!isfinite(n[0]) || !isfinite(n[1]) || !isfinite(n[2])) cnt[C_NONFIN] = 1;
+            out.phi[pos] = phiacc / (double)(L + 1);
+            out.hash[pos] = hsh;
+            cnt[C_KIND] = 0;
+            cnt[C_N] = N;
+            cnt[C_L] = L;
+            out.flops[pos] = sample_flops(p, 0, N, L, cnt, GMODE);
+#pragma unroll
+            for (int c = 0; c < C_NCNT; ++c) out.cnt[(int64_t)c * out.S + pos] = cnt[c];
+        }
+    }
+}
+
+// PI closed loop, eq. (PI), one sample per lane.  With ck != null the plant
+// state (n, I-hat) at the start of every interval i = 0, C, 2C, ... is kept
+// for the reverse pass: ck[((i / C) * 4 + f) * npi + t].
+__global__ __launch_bounds__(64) void pi_kernel(DevParams p, const int64_t* pos_list, int64_t npi,
+                                                Outs out, double* ck) {
+    const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (t >= npi) return;
+    const int64_t pos = pos_list[t];
+    const Setup su = sample_setup(p, p.id_offset + pos);
+    const double sqrtR = sqrt(p.Rmeas);
+    const double h = p.Ts / (double)p.Ns;
+    const double sqh = sqrt(h);
+    double n[3] = {su.n0[0], su.n0[1], su.n0[2]};
+    double xhat = su.xhat0, P = p.P0, Fprev = su.ubar, Ihat = 0.0, phiacc = 0.0;
+    int nonfin = 0;
+    for (int i = 0;; ++i) {
+        const double z = n[2] / p.V;
+        const double zb = setpoint(p, i, su.istep, su.sign);
+        phiacc += (z - zb) * (z - zb);
+        if (out.tz) out.tz[(int64_t)i * out.S + pos] = z;
+        if (i == su.L) break;
+        if (ck && p.ckpt_C > 0 && i % p.ckpt_C == 0) {
+            const int64_t b = (int64_t)(i / p.ckpt_C) * 4;
+            ck[(b + 0) * npi + t] = n[0];
+            ck[(b + 1) * npi + t] = n[1];
+            ck[(b + 2) * npi + t] = n[2];
+            ck[(b + 3) * npi + t] = Ihat;
+        }
+        const double y = z + p.noise_scale * sqrtR *
+                                 normal_first(p.seed, 0, (uint32_t)i, su.nid, kTagMeas);
+        if (p.run_ekf_for_pi) {
+            ekf_predict(p, xhat, P, Fprev);
+            ekf_update(p, xhat, P, y);
+            if (!isfinite(xhat) || !isfinite(P)) nonfin = 1;
+        }
+        if (out.tx) out.tx[(int64_t)i * out.S + pos] = xhat;
+        const double e = zb - y;
+        const double Ik = Ihat + p.Ts * p.kI * e;
+        const double uh = su.ubar + p.kP * e + Ik;
+        double uk = uh;
+        if (uk > p.pi_umax) uk = p.pi_umax;
+        if (uk < p.pi_umin) uk = p.pi_umin;
+        Ihat = Ik + p.Ts * p.kaw * (uh - uk);
+        const double F = uk;
+        if (out.tu) out.tu[(int64_t)i * out.S + pos] = F;
+        #pragma unroll 1
+        for (int j = 0; j < p.Ns; ++j) {
+            double xi[3];
+            process_noise(p, (uint32_t)(i * p.Ns + j), su.nid, xi);
+            em_step(p, su.k0, su.EaR, n, F, h, sqh, xi);
+        }
+        Fprev = F;
+    }
+    if (!isfinite(n[0]) || !isfinite(n[1]) || !isfinite(n[2])) nonfin = 1;
+    out.phi[pos] = phiacc / (double)(su.L + 1);
+    out.hash[pos] = 14695981039346656037ull;
+    const int vals[C_NCNT] = {1, su.N, su.L, 0, 0, 0, 0, 0, 0, 0, 0, 0, nonfin, 0, 0};
+    out.flops[pos] = sample_flops(p, 1, su.N, su.L, vals, 1);
+#pragma unroll
+    for (int c = 0; c < C_NCNT; ++c) out.cnt[(int64_t)c * out.S + pos] = vals[c];
+}
+
+// Reverse pass of the PI closed loop (pathwise, noise held fixed) from the
+// checkpoints: each segment of C intervals is recomputed forward with its
+// per-sub-step states and noise taped (tape[(step * 6 + f) * npi + t]),
+// then swept backwards.  Writes dPhi/dkP and dPhi/dkI per sample.
+__global__ __launch_bounds__(64) void pi_reverse_kernel(DevParams p, const int64_t* pos_list,
+                                                        int64_t npi, const double* ck,
+                                                        double* tape, double* iv_tape,
+                                                        double* gk /* [2][npi] */) {
+    const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (t >= npi) return;
+    const int64_t pos = pos_list[t];
+    const Setup su = sample_setup(p, p.id_offset + pos);
+    const double sqrtR = sqrt(p.Rmeas);
+    const double h = p.Ts / (double)p.Ns;
+    const double sqh = sqrt(h);
+    const double iV = 1.0 / p.V;
+    const int L = su.L, C = p.ckpt_C;
+    const double wL = 1.0 / (double)(L + 1);
+    // the final cost term z_L
+    double nb[3] = {0.0, 0.0, 0.0};
+    double Ib = 0.0, gkP = 0.0, gkI = 0.0;
+    const int nseg = (L + C - 1) / C;
+    // start: need z_L, i.e. the state after the last segment; recomputed in
+    // the last segment's forward sweep.
+    bool have_final = false;
+    for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+        const int i0 = sgi * C;
+        const int i1 = min(i0 + C, L);
+        double n[3] = {ck[((int64_t)sgi * 4 + 0) * npi + t], ck[((int64_t)sgi * 4 + 1) * npi + t],
+                       ck[((int64_t)sgi * 4 + 2) * npi + t]};
+        double Ihat = ck[((int64_t)sgi * 4 + 3) * npi + t];
+        // forward recompute of the segment, taping
+        #pragma unroll 1
+        for (int i = i0; i < i1; ++i) {
+            const int li = i - i0;
+            const double z = n[2] * iV;
+            const double xm = p.noise_scale * sqrtR *
+                              normal_first(p.seed, 0, (uint32_t)i, su.nid, kTagMeas);
+            iv_tape[((int64_t)li * 5 + 0) * npi + t] = n[0];
+            iv_tape[((int64_t)li * 5 + 1) * npi + t] = n[1];
+            iv_tape[((int64_t)li * 5 + 2) * npi + t] = n[2];
+            iv_tape[((int64_t)li * 5 + 3) * npi + t] = Ihat;
+            iv_tape[((int64_t)li * 5 + 4) * npi + t] = xm;
+            const double zb = setpoint(p, i, su.istep, su.sign);
+            const double e = zb - (z + xm);
+            const double Ik = Ihat + p.Ts * p.kI * e;
+            const double uh = su.ubar + p.kP * e + Ik;
+            double uk = uh;
+            if (uk > p.pi_umax) uk = p.pi_umax;
+            if (uk < p.pi_umin) uk = p.pi_umin;
+            Ihat = Ik + p.Ts * p.kaw * (uh - uk);
+            #pragma unroll 1
+            for (int j = 0; j < p.Ns; ++j) {
+                double xi[3];
+                process_noise(p, (uint32_t)(i * p.Ns + j), su.nid, xi);
+                const int64_t st = (int64_t)li * p.Ns + j;
+                tape[(st * 6 + 0) * npi + t] = n[0];
+                tape[(st * 6 + 1) * npi + t] = n[1];
+                tape[(st * 6 + 2) * npi + t] = n[2];
+                tape[(st * 6 + 3) * npi + t] = xi[0];
+                tape[(st * 6 + 4) * npi + t] = xi[1];
+                tape[(st * 6 + 5) * npi + t] = xi[2];
+                em_step(p, su.k0, su.EaR, n, uk, h, sqh, xi);
+            }
+        }
+        if (!have_final) {
+            // cost term of the last sample point t_L
+            const double zL = n[2] * iV;
+            nb[2] = 2.0 * (zL - setpoint(p, L, su.istep, su.sign)) * wL * iV;
+            have_final = true;
+        }
+        // reverse sweep over the segment
+        #pragma unroll 1
+        for (int i = i1 - 1; i >= i0; --i) {
+            const int li = i - i0;
+            const double n0 = iv_tape[((int64_t)li * 5 + 0) * npi + t];
+            const double n1 = iv_tape[((int64_t)li * 5 + 1) * npi + t];
+            const double n2 = iv_tape[((int64_t)li * 5 + 2) * npi + t];
+            const double Ih0 = iv_tape[((int64_t)li * 5 + 3) * npi + t];
+            const double xm = iv_tape[((int64_t)li * 5 + 4) * npi + t];
+            const double z = n2 * iV;
+            const double zb = setpoint(p, i, su.istep, su.sign);
+            const double e = zb - (z + xm);
+            const double Ik = Ih0 + p.Ts * p.kI * e;
+            const double uh = su.ubar + p.kP * e + Ik;
+            double uk = uh;
+            if (uk > p.pi_umax) uk = p.pi_umax;
+            if (uk < p.pi_umin) uk = p.pi_umin;
+            const bool inside = (uh > p.pi_umin && uh < p.pi_umax);
+            // plant: Ns Euler-Maruyama sub-steps backwards
+            double Fb = 0.0;
+            #pragma unroll 1
+            for (int j = p.Ns - 1; j >= 0; --j) {
+                const int64_t st = (int64_t)li * p.Ns + j;
+                const double a0 = tape[(st * 6 + 0) * npi + t];
+                const double a1 = tape[(st * 6 + 1) * npi + t];
+                const double a2 = tape[(st * 6 + 2) * npi + t];
+                const double x0 = tape[(st * 6 + 3) * npi + t];
+                const double x1 = tape[(st * 6 + 4) * npi + t];
+                const double x2 = tape[(st * 6 + 5) * npi + t];
+                const double cA = a0 * iV, cB = a1 * iV, cT = a2 * iV;
+                const double k = su.k0 * exp(-su.EaR / cT);
+                // dr/dn = (k cB, k cA, k EaR/cT^2 cA cB) / V ; (S r V) rows S
+                const double dr0 = k * cB * iV, dr1 = k * cA * iV;
+                const double dr2 = k * (su.EaR / (cT * cT)) * cA * cB * iV;
+                // J^T nb with J = -F/V I + S dr^T V
+                const double Snb = -nb[0] - 2.0 * nb[1] + p.beta * nb[2];
+                const double m0 = nb[0] + h * (-uk * iV * nb[0] + dr0 * p.V * Snb);
+                const double m1 = nb[1] + h * (-uk * iV * nb[1] + dr1 * p.V * Snb);
+                const double m2 = nb[2] + h * (-uk * iV * nb[2] + dr2 * p.V * Snb);
+                // dn+/dF = h (C_in - c) + sigma sqrt(h) xi
+                Fb += nb[0] * (h * (p.cAin - cA) + p.sig[0] * sqh * x0) +
+                      nb[1] * (h * (p.cBin - cB) + p.sig[1] * sqh * x1) +
+                      nb[2] * (h * (p.cTin - cT) + p.sig[2] * sqh * x2);
+                nb[0] = m0; nb[1] = m1; nb[2] = m2;
+            }
+            // PI law backwards: I-hat_i = I + Ts kaw (uh - u)
+            const double ub = Fb - Ib * p.Ts * p.kaw;
+            const double uhb = Ib * p.Ts * p.kaw + (inside ? ub : 0.0);
+            const double Ikb = uhb + Ib;
+            gkI += Ikb * p.Ts * e;
+            gkP += uhb * e;
+            const double eb = Ikb * p.Ts * p.kI + uhb * p.kP;
+            Ib = Ikb;
+            // e = zb - y, y = z + v, cost (z - zb)^2 / (L + 1)
+            const double zbar_ = -eb + 2.0 * (z - zb) * wL;
+            nb[2] += zbar_ * iV;
+        }
+    }
+    gk[t] = gkP;
+    gk[npi + t] = gkI;
+}
+
+// ------------------------------------------------------------ statistics ---
+// Deterministic reductions: a single 1024-thread block, thread t takes
+// elements t, t + 1024, ... in order, then a fixed binary tree in LDS.
+__global__ __launch_bounds__(1024) void stats_kernel(const double* phi, const int32_t* cnt,
+                                                     int64_t S, const double* flops_per,
+                                                     double* out /* see host */,
+                                                     unsigned long long* hist,
+                                                     long long* totals) {
+    __shared__ double sh[1024];
+    __shared__ double sh2[1024];
+    const int t = threadIdx.x;
+    const int32_t* kind = cnt;  // row C_KIND
+    double mean[2];
+    long long count[2] = {0, 0};
+    for (int c = 0; c < 2; ++c) {
+        double a = 0.0;
+        long long k = 0;
+        for (int64_t s = t; s < S; s += 1024)
+            if (kind[s] == c) { a += phi[s]; ++k; }
+        sh[t] = a;
+        sh2[t] = (double)k;
+        __syncthreads();
+        for (int w = 512; w > 0; w >>= 1) {
+            if (t < w) { sh[t] += sh[t + w]; sh2[t] += sh2[t + w]; }
+            __syncthreads();
+        }
+        count[c] = (long long)sh2[0];
+        mean[c] = count[c] > 0 ? sh[0] / (double)count[c] : 0.0;
+        __syncthreads();
+    }
+    for (int c = 0; c < 2; ++c) {
+        double a = 0.0;
+        for (int64_t s = t; s < S; s += 1024)
+            if (kind[s] == c) {
+                const double dlt = phi[s] - mean[c];
+                a += dlt * dlt;
+                const double v = log10(phi[s]);
+                int b;
+                if (!(v >= -4.0)) b = 0;
+                else if (v >= 4.0) b = 201;
+                else {
+                    b = (int)floor((v + 4.0) / 8.0 * 200.0);
+                    if (b > 199) b = 199;
+                    b += 1;
+                }
+                atomicAdd(&hist[c * 202 + b], 1ull);
+            }
+        sh[t] = a;
+        __syncthreads();
+        for (int w = 512; w > 0; w >>= 1) {
+            if (t < w) sh[t] += sh[t + w];
+            __syncthreads();
+        }
+        if (t == 0) {
+            out[c * 3 + 0] = (double)count[c];
+            out[c * 3 + 1] = mean[c];
+            out[c * 3 + 2] = count[c] > 1 ? sh[0] / (double)(count[c] - 1) : 0.0;
+        }
+        __syncthreads();
+    }
+    // counter totals (integers: any order) and algorithmic flops (fixed tree)
+    for (int r = 0; r < C_NCNT; ++r) {
+        long long a = 0;
+        for (int64_t s = t; s < S; s += 1024) a += cnt[(int64_t)r * S + s];
+        atomicAdd((unsigned long long*)&totals[r], (unsigned long long)a);
+    }
+    double fl[2] = {0.0, 0.0};
+    for (int64_t s = t; s < S; s += 1024) {
+        const int k = cnt[s];
+        fl[k == 0 ? 0 : 1] += flops_per[s];
+    }
+    for (int c = 0; c < 2; ++c) {
+        sh[t] = fl[c];
+        __syncthreads();
+        for (int w = 512; w > 0; w >>= 1) {
+            if (t < w) sh[t] += sh[t + w];
+            __syncthreads();
+        }
+        if (t == 0) out[6 + c] = sh[0];
+        __syncthreads();
+    }
+}
+
+// Sum of per-sample gradients over the PI samples (fixed tree, one block).
+__global__ __launch_bounds__(1024) void grad_reduce_kernel(const double* gk, int64_t npi,
+                                                           double* out) {
+    __shared__ double sh[1024];
+    const int t = threadIdx.x;
+    for (int c = 0; c < 2; ++c) {
+        double a = 0.0;
+        for (int64_t s = t; s < npi; s += 1024) a += gk[c * npi + s];
+        sh[t] = a;
+        __syncthreads();
+        for (int w = 512; w > 0; w >>= 1) {
+            if (t < w) sh[t] += sh[t + w];
+            __syncthreads();
+        }
+        if (t == 0) out[c] = sh[0];
+        __syncthreads();
+    }
+}
+
+}  // namespace mccl

@@ -46,6 +46,10 @@ BASE = dict(
     hess_warm=1,
     noise_scale=1.0,
     n_samples=1,
+    sample_id_offset=0,            # first sample id (chunks, subsets)
+    ckpt_interval=0,               # PI reverse pass checkpoint spacing (0: library default)
+    samples_per_wave=0,            # NMPC lanes per wavefront (0: library plan)
+    qp_solver=1,                   # 1 active set (+ interior-point fallback), 0 interior point
 )
 
 
