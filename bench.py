@@ -21,6 +21,10 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X: 256 CU x 128 FP64 FLOP/clk x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -41,7 +45,7 @@ def cpu_baseline(cfg, seconds):
     import numpy as np
 
     import oracle
-    cores = len(os.sched_getaffinity(0))
+    cores = min(16, len(os.sched_getaffinity(0)))  # one GPU's share of the host
     n_nmpc = cfg["kind_split"] if cfg["kind_split"] >= 0 else cfg["n_samples"]
     done, wall, batch, start = 0, 0.0, cores, 0
     while wall < seconds and start < n_nmpc:
@@ -51,6 +55,7 @@ def cpu_baseline(cfg, seconds):
         wall += time.perf_counter() - t0
         done += len(ids)
         start += len(ids)
+        log(f"cpu baseline: {done} samples, {wall:.1f} s")
     return dict(value=done / wall, unit="NMPC closed-loop sims/s", cores=cores, kind="oracle",
                 sample=f"NMPC sample ids 0..{done - 1} of the same workload ({done} closed loops, "
                        f"{wall:.1f} s wall on {cores} threads)")
@@ -74,15 +79,21 @@ def main():
             cfg["noise_mod"] = args.samples // 2
     S = cfg["n_samples"]
     camp = binding.Campaign(cfg)
-    for _ in range(args.warmup):
+    log(f"campaign {args.config}: {S} samples, launch plan {camp.plan()}")
+    for w in range(args.warmup):
         camp.run()
         camp.costs()
+        log(f"warmup step {w + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         camp.run()
+        if args.steps > 1:
+            torch.cuda.synchronize()
+            log(f"timed step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    log(f"timed region: {(t1 - t0) * 1000.0 / args.steps:.1f} ms per step")
     phi, stats = camp.costs()
     ms_kernels = camp.kernel_ms()
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
@@ -107,6 +118,7 @@ def main():
     plain = None
     if not args.no_plain and n_nmpc:
         plain = adjoint_vs_plain(cfg, args.plain_samples)
+        log("adjoint vs plain done")
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, args.cpu_seconds)
 
@@ -164,6 +176,7 @@ def adjoint_vs_plain(cfg, n):
         res[name] = dict(sims_per_s=round(n / dt, 3), nmpc_kernel_ms=round(camp.kernel_ms()[0], 3),
                          sqp_iter_per_ocp=round(st["totals"]["sqp_iter"] / st["totals"]["n_ocp"], 3))
         camp.close()
+        log(f"{name} gradient: {n} NMPC samples in {dt:.2f} s")
     rel = np.abs(phis["adjoint"][0] - phis["plain"][0]) / np.abs(phis["plain"][0])
     res["samples"] = n
     res["speedup_adjoint_over_plain"] = round(res["adjoint"]["sims_per_s"] / res["plain"]["sims_per_s"], 4)

@@ -61,7 +61,7 @@ enum {
     MC_CL_CNT_IPM_CAP,       /* QPs that hit the interior-point iteration cap   */
     MC_CL_CNT_NONFINITE,     /* 1 if a non-finite state appeared                */
     MC_CL_CNT_GRAD,          /* objective-gradient evaluations                  */
-    MC_CL_CNT_AS_ITER,       /* active-set QP iterations (factorisations)       */
+    MC_CL_CNT_AS_ITER,       /* active-set QP iterations (linear solves)        */
     MC_CL_NCNT
 };
 
@@ -121,10 +121,15 @@ typedef struct {
     double noise_scale;       /* 1 stochastic, 0 deterministic run             */
     int32_t ckpt_interval;    /* PI reverse pass: intervals per checkpoint (0 = auto) */
     int32_t samples_per_wave; /* NMPC lanes used per wavefront (0 = auto)       */
-    /* QP solver: 0 primal-dual interior point (the paper's method family);
-     * 1 primal-dual active set warm-started from the SQP multipliers, with
-     * the interior-point method as fallback when the active set has not
-     * settled after 8 factorisations.  Both return the QP's unique minimiser. */
+    /* QP solver and Hessian form: 0 primal-dual interior point on the
+     * BFGS matrix W (the paper's method family); 1 primal-dual active set on
+     * W warm-started from the SQP multipliers, with the interior-point method
+     * as fallback when the active set has not settled after 8 factorisations;
+     * 2 (default) the same active-set iteration on H = W^-1 kept by the
+     * inverse BFGS update, whose QP with |A| active bounds costs one H g
+     * product and an |A| x |A| solve (fallback: interior point on H^-1).
+     * All return the QP's unique minimiser; the SQP iterates are the same up
+     * to rounding.                                                          */
     int32_t qp_solver;
     int32_t reserved0;
 } mc_cl_params;

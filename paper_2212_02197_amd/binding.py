@@ -129,7 +129,7 @@ def params(cfg: dict) -> Params:
     p.sample_id_offset = cfg.get("sample_id_offset", 0)
     p.ckpt_interval = cfg.get("ckpt_interval", 0)
     p.samples_per_wave = cfg.get("samples_per_wave", 0)
-    p.qp_solver = cfg.get("qp_solver", 1)
+    p.qp_solver = cfg.get("qp_solver", 2)
     for a in range(3):
         p.sigma[a] = cfg["sigma"][a]
     sp_i, sp_z = cfg["sp_i"], cfg["sp_z"]

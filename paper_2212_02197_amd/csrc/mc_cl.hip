@@ -196,7 +196,7 @@ static int validate(const mc_cl_params* p) {
     if (p->kP == 0.0 || p->kI == 0.0) return MC_CL_EINVAL;
     if (p->ckpt_interval < 0 || p->samples_per_wave < 0 || p->samples_per_wave > 64)
         return MC_CL_EINVAL;
-    if (p->qp_solver != 0 && p->qp_solver != 1) return MC_CL_EINVAL;
+    if (p->qp_solver < 0 || p->qp_solver > 2) return MC_CL_EINVAL;
     if (p->sample_id_offset < 0 || p->sample_id_offset + p->n_samples > (int64_t)UINT32_MAX)
         return MC_CL_EINVAL;
     return MC_CL_OK;
@@ -235,15 +235,16 @@ static int nmax_class(int N) { return N <= 16 ? 16 : (N <= 32 ? 32 : 64); }
 // Samples per wavefront.  Per SQP iteration a wavefront spends a time in the
 // one-sample-per-lane phases that does not depend on how many of its lanes
 // carry samples (their serial RK4 chains are latency bound), plus one
-// cooperative QP per sample.  With rho = T_lane / T_qp (measured on MI355X:
-// about 46 at N = 60, scaling like 60 / N since the lane phases grow with N
-// and the QP's dependency chain with N^2), the campaign rate is proportional
-// to  resident_waves(spw) * spw / (rho + spw).  Pick the best of 8..64.
+// cooperative visit (BFGS update and QP) per sample.  With
+// rho = T_lane / T_visit (measured on MI355X with the inverse-form QP: about
+// 85 at N = 60, scaling like 60 / N since the lane phases grow with N and
+// the visit with N^2), the campaign rate is proportional to
+// resident_waves(spw) * spw / (rho + spw).  Pick the best of 1..64.
 static int choose_spw(int64_t count, int N, int slots_full) {
-    const double rho = 46.0 * 60.0 / (double)std::max(N, 1);
+    const double rho = 85.0 * 60.0 / (double)std::max(N, 1);
     int best = 64;
     double best_rate = -1.0;
-    for (int spw = 64; spw >= 8; spw >>= 1) {
+    for (int spw = 64; spw >= 1; spw >>= 1) {
         const int64_t groups = (count + spw - 1) / spw;
         const double resident = (double)std::min<int64_t>(groups, slots_full);
         const double rate = resident * spw / (rho + spw);

@@ -20,42 +20,83 @@
 
 namespace mccl {
 
+typedef __attribute__((address_space(3))) double lds_double;
+
+// Wave-uniform copies of values that arrive in VGPRs (function arguments).
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni_u64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ double uni_d(double v) {
+    return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                            __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
+
 __device__ __forceinline__ double readlane_d(double v, int lane) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
     return __hiloint2double(hi, lo);
 }
 
+// Wavefront reductions by DPP lane shuffles (VALU only, no LDS round
+// trip): pairs, quads, 8-lane and 16-lane rows, then the row broadcasts
+// 15 and 31 fold the four rows into lane 63, whose value is returned to
+// every lane.  The order of the operations is fixed, so the result is
+// deterministic and the same on all lanes.  `id` is the operation's
+// identity (what a lane outside the selected rows contributes).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_d(double old, double v) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, ROWMASK,
+                                               0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, ROWMASK,
+                                               0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <typename Op>
+__device__ __forceinline__ double wave_reduce(double v, double id, Op op) {
+    v = op(v, dpp_d<0xB1, 0xf>(id, v));    // quad_perm [1,0,3,2]
+    v = op(v, dpp_d<0x4E, 0xf>(id, v));    // quad_perm [2,3,0,1]
+    v = op(v, dpp_d<0x124, 0xf>(id, v));   // row_ror:4
+    v = op(v, dpp_d<0x128, 0xf>(id, v));   // row_ror:8
+    v = op(v, dpp_d<0x142, 0xa>(id, v));   // row_bcast:15 into rows 1, 3
+    v = op(v, dpp_d<0x143, 0xc>(id, v));   // row_bcast:31 into rows 2, 3
+    return readlane_d(v, 63);
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return wave_reduce(v, 0.0, [](double a, double b) { return a + b; });
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    return wave_reduce(v, -__builtin_inf(), [](double a, double b) { return fmax(a, b); });
 }
 __device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
+    return wave_reduce(v, __builtin_inf(), [](double a, double b) { return fmin(a, b); });
 }
 
 // Stage the sample's W (NMAX x NMAX doubles, 16-byte aligned) into LDS with
 // direct global-to-LDS loads: 1 KB per instruction, no registers involved,
-// all in flight together, one wait.
+// all in flight together.  coop_stage_issue waits for this wave's earlier
+// stores (to W among them) and issues the loads; coop_stage_wait waits for
+// every load in flight (other loads issued in between complete with them).
 template <int NMAX>
-__device__ __forceinline__ void coop_stage(const double* __restrict__ Wg, double* Wl, int lane) {
+__device__ __forceinline__ void coop_stage_issue(const double* __restrict__ Wg, double* Wl, int lane) {
     static_assert((NMAX * NMAX) % 128 == 0, "W must fill whole 1 KB rows");
-    __builtin_amdgcn_s_waitcnt(0x0F70);   // earlier stores to W have landed
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): earlier stores to W have landed
 #pragma unroll
     for (int q = 0; q < NMAX * NMAX / 128; ++q)
         __builtin_amdgcn_global_load_lds(
             (const void __attribute__((address_space(1)))*)(Wg + q * 128 + 2 * lane),
             (void __attribute__((address_space(3)))*)(Wl + q * 128), 16, 0, 0);
+}
+__device__ __forceinline__ void coop_stage_wait() {
     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     __syncthreads();
+}
+template <int NMAX>
+__device__ __forceinline__ void coop_stage(const double* __restrict__ Wg, double* Wl, int lane) {
+    coop_stage_issue<NMAX>(Wg, Wl, lane);
+    coop_stage_wait();
 }
 
 // 1/sqrt(a) and sqrt(a) from the hardware reciprocal square root refined by
@@ -390,18 +431,19 @@ __device__ __forceinline__ int coop_bfgs(double* Wl, double* __restrict__ Wg, in
     return 1;
 }
 
-// W <- I on the sample's N x N block, in global memory and (when Wl is
-// given) in its staged LDS copy.
+// W <- I (equally H <- I) in global memory and (when Wl is given) in its
+// staged LDS copy.  The whole NMAX x NMAX block is written: entries beyond
+// the sample's N x N block are never read unmasked.
 template <int NMAX>
 __device__ __forceinline__ void coop_identity(double* Wl, double* __restrict__ Wg, int N, int lane) {
-    if (lane < N) {
+    (void)N;
+    if (lane < NMAX) {
 #pragma unroll
-        for (int j = 0; j < NMAX; ++j)
-            if (j < N) {
-                const double v = (j == lane) ? 1.0 : 0.0;
-                Wg[j * NMAX + lane] = v;
-                if (Wl) Wl[j * NMAX + lane] = v;
-            }
+        for (int j = 0; j < NMAX; ++j) {
+            const double v = (j == lane) ? 1.0 : 0.0;
+            Wg[j * NMAX + lane] = v;
+            if (Wl) Wl[j * NMAX + lane] = v;
+        }
     }
     __syncthreads();
 }
@@ -425,6 +467,312 @@ __device__ __forceinline__ void coop_shift(const double* Wl, double* __restrict_
         }
     }
     __syncthreads();
+}
+
+
+// ---------------------------------------------------------------------------
+// Inverse-Hessian form.  The sample keeps H = W^-1 (same layout as W, in
+// global memory, staged to LDS per visit) and diag(W).  With H the QP of a
+// fixed active set A needs no factorisation of W: from W d + g - lam = 0
+// (lam_i > 0 on a lower bound, < 0 on an upper bound, 0 on free inputs),
+// d = -H g + H[:, A] lam_A and d_A on its bounds give
+// H_AA lam_A = d_A + (H g)_A, an |A| x |A| system.  The BFGS update of W
+// maps to the product form of the inverse update, and W d = lam - g from
+// the QP supplies W s for the damping.  Mathematically the iterates are
+// those of the W form; the work per SQP iteration is O(N^2 + |A|^3).
+
+// Rows of the sample's NMAX x NMAX block that a loop visits: N rounded up
+// to a multiple of 8.  Outside its N x N block the block holds the
+// identity (written whole at every reset; updates and shifts touch only
+// the N x N block), so for lanes < N the extra rows are zero, and the
+// vectors broadcast across them are zero on lanes >= N.
+template <int NMAX>
+__device__ __forceinline__ int rows8(int N) {
+    const int r = (N + 7) & ~7;
+    return r < NMAX ? r : NMAX;
+}
+
+// (H x)_i on lane i < N from the staged H (lane i reads its column, H
+// symmetric); x_j is broadcast from lane j and must be 0 on lanes >= N;
+// the result is 0 on lanes >= N.  Eight rows per step with their LDS
+// reads issued one step ahead; four partial sums.
+template <int NMAX>
+__device__ __forceinline__ double coop_matvec(const double* Hl, int N, int lane, double x) {
+    const int lc = lane < NMAX ? lane : NMAX - 1;
+    const int R = rows8<NMAX>(N);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double h[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) h[q] = Hl[q * NMAX + lc];
+    #pragma unroll 1
+    for (int j = 0; j < R; j += 8) {
+        double hn[8];
+        const int jn = j + 8 < R ? j + 8 : j;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) hn[q] = Hl[(jn + q) * NMAX + lc];
+        a0 = fma(h[0], readlane_d(x, j + 0), a0);
+        a1 = fma(h[1], readlane_d(x, j + 1), a1);
+        a2 = fma(h[2], readlane_d(x, j + 2), a2);
+        a3 = fma(h[3], readlane_d(x, j + 3), a3);
+        a0 = fma(h[4], readlane_d(x, j + 4), a0);
+        a1 = fma(h[5], readlane_d(x, j + 5), a1);
+        a2 = fma(h[6], readlane_d(x, j + 6), a2);
+        a3 = fma(h[7], readlane_d(x, j + 7), a3);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) h[q] = hn[q];
+    }
+    const double acc = (a0 + a1) + (a2 + a3);
+    return lane < N ? acc : 0.0;
+}
+
+// Damped BFGS of the SQP section in inverse form.  Lane i < N passes s_i,
+// y_i, v_i = (W s)_i and diag(W)_ii (updated in place).  theta rule 0.2 /
+// 0.8, r = theta y + (1 - theta) W s, skipped when min(s'Ws, s'r) <= eps_m;
+// otherwise, with rho = 1 / s'r,
+//   H+ = (I - rho s r') H (I - rho r s') + rho s s'
+//      = H - rho (s (Hr)' + (Hr) s') + (rho^2 r'Hr + rho) s s',
+// the exact inverse of W - Ws (Ws)'/s'Ws + r r'/s'r, and
+//   diag(W+)_ii = W_ii - v_i^2 / s'Ws + r_i^2 / s'r.
+// The staged copy Hl and the global H are both updated.  Returns 1 if
+// updated; fl receives the FP64 work.
+template <int NMAX>
+__device__ __forceinline__ int coop_bfgs_h(double* Hl, double* __restrict__ Hg, int N, int lane,
+                                           double s, double y, double v, double& wd, double& fl) {
+    const bool act = lane < N;
+    if (!act) { s = 0.0; y = 0.0; v = 0.0; }
+    const double n = N;
+    const double sWs = wave_sum(s * v);
+    const double sy = wave_sum(s * y);
+    const double theta = (sy >= 0.2 * sWs) ? 1.0 : 0.8 * sWs / (sWs - sy);
+    const double r = act ? theta * y + (1.0 - theta) * v : 0.0;
+    const double sr = wave_sum(s * r);
+    const double kappa = sWs < sr ? sWs : sr;
+    fl += 9.0 * n;
+    if (!(kappa > DBL_EPSILON)) return 0;
+    const double Hr = coop_matvec<NMAX>(Hl, N, lane, r);
+    const double rHr = wave_sum(r * Hr);
+    const double rho = 1.0 / sr;
+    const double c = rho * rho * rHr + rho;
+    const double a1 = c * s - rho * Hr;   // multiplies s_j
+    const double a2 = -rho * s;           // multiplies (Hr)_j
+    __syncthreads();   // every lane has read H for Hr
+    if (act) {
+        // rows N..R-1 see s_j = (Hr)_j = 0 and are written back unchanged
+        const int R = rows8<NMAX>(N);
+        #pragma unroll 1
+        for (int j = 0; j < R; j += 8) {
+            double t[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) t[q] = Hl[(j + q) * NMAX + lane];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                t[q] = fma(a2, readlane_d(Hr, j + q), fma(a1, readlane_d(s, j + q), t[q]));
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                Hl[(j + q) * NMAX + lane] = t[q];
+                Hg[(j + q) * NMAX + lane] = t[q];
+            }
+        }
+    }
+    if (act) wd = (wd - v * v / sWs) + r * r / sr;
+    __syncthreads();
+    fl += 6.0 * n * n + 14.0 * n;
+    return 1;
+}
+
+// H_AA x = b_A for the active set `amask` (m = |A| <= MM bits), with the
+// system compressed onto lanes 0..m-1: lane k holds row k of H_AA, gathered
+// from the staged H.  Lane i in A passes b_i and receives x for its
+// variable in `lam`; xc (lane k) is the compressed solution.  Returns
+// false on a non-positive pivot.
+template <int NMAX, int MM>
+__device__ __forceinline__ bool coop_active_solve(const double* Hl, uint64_t amask, int m, int lane,
+                                                  double b, double& lam, double& xc) {
+    int myvar = 0;
+    {
+        uint64_t mm = amask;
+#pragma unroll
+        for (int k = 0; k < MM; ++k) {
+            const int a = mm ? __ffsll((unsigned long long)mm) - 1 : 0;
+            mm &= mm - 1;
+            myvar = (lane == k) ? a : myvar;
+        }
+    }
+    const bool row = lane < m;
+    double Lx[MM];
+    {
+        uint64_t mm = amask;
+#pragma unroll
+        for (int jj = 0; jj < MM; ++jj) {
+            const int a = mm ? __ffsll((unsigned long long)mm) - 1 : 0;
+            mm &= mm - 1;
+            const double h = Hl[a * NMAX + myvar];
+            Lx[jj] = (row && jj < m) ? h : ((jj == lane) ? 1.0 : 0.0);
+        }
+    }
+    const double bk = __shfl(b, myvar, 64);
+    double myinv;
+    const bool ok = coop_cholesky<MM>(Lx, lane, myinv);
+    xc = coop_solve<MM>(Lx, lane, myinv, row ? bk : 0.0);
+    const int rank = __popcll(amask & ((1ull << lane) - 1ull));
+    const double xl = __shfl(xc, rank < 64 ? rank : 0, 64);
+    lam = ((amask >> lane) & 1ull) ? xl : 0.0;
+    return ok;
+}
+
+struct SolveOut {
+    double lam, xc;
+    int ok;
+};
+
+// The same as a separate function (not inlined): the factor's registers and
+// the unrolled code stay out of the QP loop, whose register allocation
+// would otherwise hoist the identity padding out of the loop and spill it.
+template <int NMAX, int MM>
+__device__ __noinline__ SolveOut coop_active_solve_far(lds_double* Hl3, uint64_t amask, int m,
+                                                       double b) {
+    SolveOut o{0.0, 0.0, 0};
+    o.ok = coop_active_solve<NMAX, MM>((const double*)Hl3, uni_u64(amask), uni(m), (int)threadIdx.x,
+                                       b, o.lam, o.xc);
+    return o;
+}
+
+// Box QP  min 1/2 d'Wd + g'd,  umin - u <= d <= umax - u  by the
+// primal-dual active-set iteration in inverse form.  The set prediction
+// uses lam + W_ii (bound - d), the rule of the Jacobi-scaled variables of
+// coop_box_qp_as written back in the original ones.  Lane i < N passes
+// g_i, u_i, the multiplier estimate lam0_i = pi_l,i - pi_u,i and W_ii;
+// it receives d_i, nu_l,i, nu_u,i and (W d)_i = lam_i - g_i.  Status 2:
+// sets still changing after max_iter solves; -1: H_AA not positive
+// definite.
+template <int NMAX>
+__device__ __forceinline__ QPResult coop_box_qp_h(const double* Hl, lds_double* Hl3, int N, int lane, double wd, double g, double u,
+                                                  double lam0, double umin, double umax,
+                                                  int max_iter, double& d_out, double& nl_out,
+                                                  double& nu_out, double& Wd_out, double& fl) {
+    const bool act = lane < N;
+    const int lc = lane < NMAX ? lane : NMAX - 1;
+    const double n = N;
+    QPResult res{0, 0};
+    const double lo = act ? umin - u : -1.0;
+    const double hi = act ? umax - u : 1.0;
+    const double hg = coop_matvec<NMAX>(Hl, N, lane, act ? g : 0.0);
+    fl += 2.0 * n * n;
+    double d = 0.0, lam = act ? lam0 : 0.0;
+    int prev = -1, st = 0;
+    for (int it = 0;; ++it) {
+        st = 0;
+        if (act) {
+            if (lam + wd * (lo - d) > 0.0) st = 1;
+            else if (lam + wd * (hi - d) < 0.0) st = 2;
+        }
+        if (it > 0 && !__ballot(st != prev)) {
+            res.iters = it;
+            break;
+        }
+        if (it == max_iter) {
+            res.status = 2;
+            res.iters = it;
+            break;
+        }
+        prev = st;
+        const uint64_t amask = __ballot(st != 0);
+        const int m = __popcll(amask);
+        const double dA = st == 1 ? lo : (st == 2 ? hi : 0.0);
+        double acc = -hg;
+        lam = 0.0;
+        if (m > 0) {
+            const double b = dA + hg;
+            double xc = 0.0;
+            bool ok;
+            SolveOut so{0.0, 0.0, 0};
+            if (m <= 8) {
+                so = coop_active_solve_far<NMAX, 8>(Hl3, amask, m, b);
+            } else if (m <= 16 || NMAX <= 16) {
+                so = coop_active_solve_far<NMAX, 16>(Hl3, amask, m, b);
+            } else if constexpr (NMAX > 16) {
+                if constexpr (NMAX > 32) {
+                    so = m > 32 ? coop_active_solve_far<NMAX, 64>(Hl3, amask, m, b)
+                                : coop_active_solve_far<NMAX, 32>(Hl3, amask, m, b);
+                } else {
+                    so = coop_active_solve_far<NMAX, 32>(Hl3, amask, m, b);
+                }
+            }
+            ok = so.ok;
+            lam = so.lam;
+            xc = so.xc;
+            uint64_t mm = amask;
+            #pragma unroll 1
+            for (int k = 0; k < m; ++k) {
+                const int a = __ffsll((unsigned long long)mm) - 1;
+                mm &= mm - 1;
+                acc = fma(Hl[a * NMAX + lc], readlane_d(xc, k), acc);
+            }
+            const double mf = m;
+            fl += mf * mf * mf / 3.0 + 2.0 * mf * mf + 2.0 * n * mf;
+        }
+        fl += 6.0 * n;
+        d = act ? (st ? dA : acc) : 0.0;
+    }
+    d_out = st == 1 ? lo : (st == 2 ? hi : d);
+    nl_out = lam > 0.0 ? lam : 0.0;
+    nu_out = lam < 0.0 ? -lam : 0.0;
+    Wd_out = act ? lam - g : 0.0;
+    return res;
+}
+
+// W = H^-1 into Wl (the staged buffer, overwriting H): Cholesky of H, then
+// one solve per column.  For the rare QPs the active-set iteration leaves
+// unsettled, which go to the interior-point method on W.  Returns false if
+// H is not positive definite.
+template <int NMAX>
+__device__ __forceinline__ bool coop_invert(double* Hl, int N, int lane, double& fl) {
+    const int lc = lane < NMAX ? lane : NMAX - 1;
+    double Lx[NMAX];
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+        const double h = Hl[j * NMAX + lc];
+        Lx[j] = lane < N ? ((j < N) ? h : 0.0) : ((j == lane) ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    double myinv;
+    if (!coop_cholesky<NMAX>(Lx, lane, myinv)) return false;
+    #pragma unroll 1
+    for (int j = 0; j < N; ++j) {
+        const double x = coop_solve<NMAX>(Lx, lane, myinv, lane == j ? 1.0 : 0.0);
+        if (lane < N) Hl[j * NMAX + lane] = x;
+    }
+    __syncthreads();
+    const double n = N;
+    fl += n * n * n / 3.0 + 2.0 * n * n * n;
+    return true;
+}
+
+// Shift of H for the next OCP.  The W form drops u_0's row and column and
+// repeats the last diagonal entry uncoupled; in inverse form the leading
+// block becomes the inverse of W[1:, 1:], i.e. the Schur complement
+// H[1:, 1:] - H[1:, 0] H[0, 1:] / H_00, and the last diagonal entry
+// 1 / W_{N-1,N-1}.  From the staged copy Hl into global Hg.
+template <int NMAX>
+__device__ __forceinline__ void coop_shift_h(const double* Hl, double* __restrict__ Hg, int N,
+                                             int lane, double wlast, double& fl) {
+    const double inv_e = 1.0 / Hl[0];
+    const int li = lane + 1 < NMAX ? lane + 1 : NMAX - 1;
+    const double fi = (lane + 1 < N) ? Hl[li] : 0.0;   // H_0,i+1
+    const double hlast = 1.0 / wlast;
+    if (lane < N) {
+        #pragma unroll 4
+        for (int j = 0; j < N; ++j) {
+            const int jr = j + 1 < NMAX ? j + 1 : NMAX - 1;
+            const double p = readlane_d(fi, j) * fi;
+            double w = Hl[jr * NMAX + li] - p * inv_e;
+            if (!(lane < N - 1 && j < N - 1)) w = (lane == N - 1 && j == N - 1) ? hlast : 0.0;
+            Hg[j * NMAX + lane] = w;
+        }
+    }
+    __syncthreads();
+    const double n = N;
+    fl += 3.0 * n * n;
 }
 
 }  // namespace mccl

@@ -40,7 +40,8 @@ struct Outs {
 
 // Lane-tiled per-sample vectors of the SQP (element k of lane l's sample at
 // base[(v * NMAX + k) * 64 + l]).
-enum : int { V_U = 0, V_G, V_D, V_PIL, V_PIU, V_NL, V_NU, V_S, V_Y, V_COUNT };
+// V_WD: diag(W) and V_V: W d, then W s after the line search (inverse form).
+enum : int { V_U = 0, V_G, V_D, V_PIL, V_PIU, V_NL, V_NU, V_S, V_Y, V_WD, V_V, V_COUNT };
 
 struct NmpcWork {
     const int64_t* pos;  // sample positions, grouped by spw
@@ -78,8 +79,13 @@ __device__ __forceinline__ int wave_max_i(int v) {
 //   active-set iteration N^3/3 + 6 N^2 + 10 N,
 //   BFGS 2 N^2 + 9 N per attempt + 6 N^2 per applied update,
 //   SQP bookkeeping 16 N per iteration.
+// The inverse form (qp_solver 2) accumulates its QP, BFGS and shift work in
+// `coop` as it runs (it depends on the active-set sizes): H g 2 N^2 per QP,
+// per active-set solve m^3/3 + 2 m^2 + 2 N m + 6 N, BFGS 6 N^2 + 23 N per
+// applied update (9 N if skipped), shift 3 N^2, inversion for the
+// interior-point fallback 7 N^3 / 3; interior-point iterations as above.
 __device__ __forceinline__ double sample_flops(const DevParams& p, int kind, int N, int L,
-                                               const int (&c)[C_NCNT], int gmode) {
+                                               const int (&c)[C_NCNT], int gmode, double coop) {
     const double Ns = p.Ns, Nc = p.Nc, n = N, l = L;
     double fl = 3.0 * (l + 1.0) + l * (8.0 + 52.0 * Ns);
     if (kind == 0 || p.run_ekf_for_pi) fl += l * (142.0 * Nc + 12.0);
@@ -89,9 +95,213 @@ __device__ __forceinline__ double sample_flops(const DevParams& p, int kind, int
                                    : 117.0 * n * Nc + 13.0 * Nc * n * (n + 1.0) + n * (n + 1.0) + 6.0 * n;
     const double ipm = n * n * n / 3.0 + 7.0 * n * n + 60.0 * n;
     const double asi = n * n * n / 3.0 + 6.0 * n * n + 10.0 * n;
-    fl += (double)c[C_LS] * shoot + (double)c[C_GRAD] * grad + (double)c[C_IPM] * ipm +
-          (double)c[C_AS] * asi;
+    fl += (double)c[C_LS] * shoot + (double)c[C_GRAD] * grad + (double)c[C_IPM] * ipm;
+    if (p.qp_solver == 2) return fl + coop + (double)c[C_SQP] * 16.0 * n;
+    fl += (double)c[C_AS] * asi;
     fl += (double)c[C_SQP] * (2.0 * n * n + 9.0 * n + 16.0 * n) + (double)(c[C_SQP] - c[C_SKIP]) * 6.0 * n * n;
+    return fl;
+}
+
+// ---------------------------------------------------------------------------
+// Cooperative visits.  Each is a separate (not inlined) function so that its
+// register allocation is its own: the closed loop's per-lane state stays
+// out of the dense phase and the rarely taken paths stay out of the hot one.
+// Arguments arrive in VGPRs; the wave-uniform ones are re-established as
+// such with readfirstlane.  The staging buffer is passed as an LDS pointer.
+
+// Counter deltas and FP64 work of one visit (wave-uniform).
+struct VisitOut {
+    double fl;
+    int skip, reset, ipm, as, sqp, ipmcap;
+};
+
+// H (or W) <- I in global memory and the staged copy: the rare reset after
+// a non-positive pivot, out of line so that the identity's constants are
+// not hoisted into the common path.
+template <int NMAX>
+__device__ __noinline__ void coop_reset(double* Ws, lds_double* Wl3) {
+    coop_identity<NMAX>((double*)Wl3, Ws, NMAX, (int)threadIdx.x);
+}
+
+// Interior-point fallback of the inverse form on W = H^-1 (rare).
+struct FallbackOut {
+    double d, nl, nu, fl;
+    int status, iters;
+};
+template <int NMAX>
+__device__ __noinline__ FallbackOut coop_ipm_fallback(lds_double* Hl3, int N, double g, double u,
+                                                      double umin, double umax, int max_iter) {
+    double* Wl = (double*)Hl3;
+    N = uni(N);
+    const int lane = threadIdx.x;
+    FallbackOut o{0.0, 0.0, 0.0, 0.0, -1, 0};
+    double Dg = 1.0;
+    if (coop_invert<NMAX>(Wl, N, lane, o.fl) && coop_scale<NMAX>(Wl, N, lane, Dg)) {
+        const QPResult r = coop_box_qp<NMAX>(Wl, N, lane, Dg, g, u, uni_d(umin), uni_d(umax),
+                                             uni(max_iter), o.d, o.nl, o.nu);
+        o.status = r.status;
+        o.iters = r.iters;
+    }
+    return o;
+}
+
+// Inverse-form visit of sample s: stage H, the pending BFGS update, then
+// the QP if the sample is still iterating.  A QP whose active set has not
+// settled goes to the interior-point method on W = H^-1; H_AA or W not
+// positive definite resets H = I (and diag W = 1) once.
+template <int NMAX>
+__device__ __forceinline__ VisitOut coop_visit_h(double* TB, double* Ws, lds_double* Wl3, int Ns_, int s,
+                                              int flags, double umin, double umax, int ipm_max_iter) {
+    double* const Wl = (double*)Wl3;
+    const int lane = threadIdx.x;
+    Ns_ = uni(Ns_);
+    s = uni(s);
+    flags = uni(flags);
+    umin = uni_d(umin);
+    umax = uni_d(umax);
+    VisitOut vo{0.0, 0, 0, 0, 0, 0, 0};
+    const bool in = lane < Ns_;
+    double* const wdp = TB + (V_WD * NMAX + lane) * 64 + s;
+    // the sample's vectors (column s of the lane tiles) are loaded while H
+    // is being staged
+    coop_stage_issue<NMAX>(Ws, Wl, lane);
+    const int lt = in ? lane : 0;
+    const double* const tcol = TB + lt * 64 + s;
+    double wd = tcol[V_WD * NMAX * 64], si = tcol[V_S * NMAX * 64], yi = tcol[V_Y * NMAX * 64];
+    double vi = tcol[V_V * NMAX * 64], gi = tcol[V_G * NMAX * 64], ui = tcol[V_U * NMAX * 64];
+    double li = tcol[V_PIL * NMAX * 64] - tcol[V_PIU * NMAX * 64];
+    coop_stage_wait();
+    if (!in) { wd = 1.0; si = yi = vi = gi = ui = li = 0.0; }
+    if (flags & 1) {
+        const int upd = coop_bfgs_h<NMAX>(Wl, Ws, Ns_, lane, si, yi, vi, wd, vo.fl);
+        if (!upd) vo.skip = 1;
+        if (upd && in) *wdp = wd;
+    }
+    if (flags & 2) {
+        double d = 0.0, nl = 0.0, nu = 0.0, wdd = 0.0;
+        QPResult r{0, 0};
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            if (attempt == 1) {
+                vo.reset++;
+                coop_reset<NMAX>(Ws, Wl3);
+                wd = 1.0;
+                if (in) *wdp = 1.0;
+            }
+            if (__ballot(in && !(wd > 0.0))) {
+                r.status = -1;
+                continue;
+            }
+            r = coop_box_qp_h<NMAX>(Wl, Wl3, Ns_, lane, wd, gi, ui, li, umin, umax, 8, d, nl, nu, wdd,
+                                    vo.fl);
+            vo.as += r.iters;
+            if (r.status == 2) {
+                const FallbackOut fb = coop_ipm_fallback<NMAX>(Wl3, Ns_, gi, ui, umin, umax, ipm_max_iter);
+                vo.fl += fb.fl;
+                vo.ipm += fb.iters;
+                r.status = fb.status;
+                r.iters = fb.iters;
+                d = fb.d;
+                nl = fb.nl;
+                nu = fb.nu;
+                wdd = in ? (nl - nu) - gi : 0.0;
+            }
+            if (r.status != -1) break;
+        }
+        vo.sqp = 1;
+        if (r.status == 1) vo.ipmcap = 1;
+        if (in) {
+            TB[(V_D * NMAX + lane) * 64 + s] = d;
+            TB[(V_NL * NMAX + lane) * 64 + s] = nl;
+            TB[(V_NU * NMAX + lane) * 64 + s] = nu;
+            TB[(V_V * NMAX + lane) * 64 + s] = wdd;
+        }
+    }
+    __syncthreads();
+    return vo;
+}
+
+// W-form visit (qp_solver 0: interior point, 1: active set with the
+// interior-point method as fallback) of sample s: stage W, the pending
+// BFGS update, then the QP.  A non-positive pivot or diagonal (W not
+// positive definite) resets W = I and solves again.
+template <int NMAX>
+__device__ __noinline__ VisitOut coop_visit_w(double* TB, double* Ws, lds_double* Wl3, int Ns_, int s,
+                                              int flags, double umin, double umax, int ipm_max_iter,
+                                              int qp_solver) {
+    double* const Wl = (double*)Wl3;
+    const int lane = threadIdx.x;
+    Ns_ = uni(Ns_);
+    s = uni(s);
+    flags = uni(flags);
+    qp_solver = uni(qp_solver);
+    ipm_max_iter = uni(ipm_max_iter);
+    umin = uni_d(umin);
+    umax = uni_d(umax);
+    VisitOut vo{0.0, 0, 0, 0, 0, 0, 0};
+    const bool in = lane < Ns_;
+    coop_stage<NMAX>(Ws, Wl, lane);
+    if (flags & 1) {
+        const double si = in ? TB[(V_S * NMAX + lane) * 64 + s] : 0.0;
+        const double yi = in ? TB[(V_Y * NMAX + lane) * 64 + s] : 0.0;
+        if (!coop_bfgs<NMAX>(Wl, Ws, Ns_, lane, si, yi)) vo.skip = 1;
+    }
+    if (flags & 2) {
+        const double gi = in ? TB[(V_G * NMAX + lane) * 64 + s] : 0.0;
+        const double ui = in ? TB[(V_U * NMAX + lane) * 64 + s] : 0.0;
+        const double li = in ? TB[(V_PIL * NMAX + lane) * 64 + s] - TB[(V_PIU * NMAX + lane) * 64 + s]
+                             : 0.0;
+        double d = 0.0, nl = 0.0, nu = 0.0, Dg = 1.0;
+        QPResult r{0, 0};
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            if (attempt == 1) {
+                vo.reset++;
+                coop_reset<NMAX>(Ws, Wl3);
+            }
+            if (!coop_scale<NMAX>(Wl, Ns_, lane, Dg)) {
+                r.status = -1;
+                continue;
+            }
+            r.status = 2;
+            if (qp_solver == 1) {
+                r = coop_box_qp_as<NMAX>(Wl, Ns_, lane, Dg, gi, ui, li, umin, umax, 8, d, nl, nu);
+                vo.as += r.iters;
+            }
+            if (r.status == 2) {
+                r = coop_box_qp<NMAX>(Wl, Ns_, lane, Dg, gi, ui, umin, umax, ipm_max_iter, d, nl, nu);
+                vo.ipm += r.iters;
+            }
+            if (r.status != -1) break;
+        }
+        vo.sqp = 1;
+        if (r.status == 1) vo.ipmcap = 1;
+        if (in) {
+            TB[(V_D * NMAX + lane) * 64 + s] = d;
+            TB[(V_NL * NMAX + lane) * 64 + s] = nl;
+            TB[(V_NU * NMAX + lane) * 64 + s] = nu;
+        }
+    }
+    __syncthreads();
+    return vo;
+}
+
+// Hessian shift for the next OCP (W or inverse form) of sample s; returns
+// the FP64 work.
+template <int NMAX>
+__device__ __noinline__ double coop_visit_shift(double* TB, double* Ws, lds_double* Wl3, int Ns_,
+                                                int s, int inverse) {
+    double* const Wl = (double*)Wl3;
+    const int lane = threadIdx.x;
+    Ns_ = uni(Ns_);
+    s = uni(s);
+    inverse = uni(inverse);
+    coop_stage<NMAX>(Ws, Wl, lane);
+    double fl = 0.0;
+    if (inverse) {
+        const double wlast = TB[(V_WD * NMAX + Ns_ - 1) * 64 + s];
+        coop_shift_h<NMAX>(Wl, Ws, Ns_, lane, wlast, fl);
+    } else {
+        coop_shift<NMAX>(Wl, Ws, Ns_, lane);
+    }
     return fl;
 }
 
@@ -101,7 +311,7 @@ __device__ __forceinline__ double sample_flops(const DevParams& p, int kind, int
 template <int NMAX, int GMODE>
 __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, int i, const Setup& su,
                           double xhat, int lane, double* TB, double* XS, double* Wslot,
-                          double* Wl, double* lds, int (&cnt)[C_NCNT]) {
+                          double* Wl, int (&cnt)[C_NCNT], double& qfl) {
     double* const U = TB + (V_U * NMAX) * 64 + lane;
     double* const G = TB + (V_G * NMAX) * 64 + lane;
     double* const Dv = TB + (V_D * NMAX) * 64 + lane;
@@ -111,11 +321,14 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
     double* const NUv = TB + (V_NU * NMAX) * 64 + lane;
     double* const Sv = TB + (V_S * NMAX) * 64 + lane;
     double* const Yv = TB + (V_Y * NMAX) * 64 + lane;
+    double* const WDv = TB + (V_WD * NMAX) * 64 + lane;
+    double* const Vv = TB + (V_V * NMAX) * 64 + lane;
     double* const Xs = XS + lane;
     static constexpr double smax = 100.0;
 
     double f = 0.0;
     if (live) {
+        const bool fresh = i == 0 || !p.hess_warm;
         #pragma unroll 1
         for (int k = 0; k < N; ++k) {
             double v = U[k * 64];
@@ -124,6 +337,7 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
             U[k * 64] = v;
             PIL[k * 64] = 0.0;
             PIU[k * 64] = 0.0;
+            if (fresh) WDv[k * 64] = 1.0;
         }
     }
     // W = I for the first OCP (and every OCP without the warm start)
@@ -172,59 +386,21 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
             m &= m - 1;
             const int Ns_ = __builtin_amdgcn_readlane(N, s);
             double* Ws = Wslot + (int64_t)s * NMAX * NMAX;
-            const bool in = lane < Ns_;
-            coop_stage<NMAX>(Ws, Wl, lane);
-            if ((mp >> s) & 1ull) {
-                const double si = in ? TB[(V_S * NMAX + lane) * 64 + s] : 0.0;
-                const double yi = in ? TB[(V_Y * NMAX + lane) * 64 + s] : 0.0;
-                const int upd = coop_bfgs<NMAX>(Wl, Ws, Ns_, lane, si, yi);
-                if (lane == s && !upd) cnt[C_SKIP]++;
-            }
-            if ((ma >> s) & 1ull) {
-                const double gi = in ? TB[(V_G * NMAX + lane) * 64 + s] : 0.0;
-                const double ui = in ? TB[(V_U * NMAX + lane) * 64 + s] : 0.0;
-                const double li = in ? TB[(V_PIL * NMAX + lane) * 64 + s] -
-                                           TB[(V_PIU * NMAX + lane) * 64 + s]
-                                     : 0.0;
-                double d = 0.0, nl = 0.0, nu = 0.0, Dg = 1.0;
-                QPResult r{0, 0};
-                int its = 0, ases = 0;
-                // a non-positive pivot or diagonal (W not positive definite):
-                // W <- I, solve again
-                for (int attempt = 0; attempt < 2; ++attempt) {
-                    if (attempt == 1) {
-                        if (lane == s) cnt[C_RESET]++;
-                        coop_identity<NMAX>(Wl, Ws, Ns_, lane);
-                    }
-                    if (!coop_scale<NMAX>(Wl, Ns_, lane, Dg)) {
-                        r.status = -1;
-                        continue;
-                    }
-                    r.status = 2;
-                    if (p.qp_solver == 1) {
-                        r = coop_box_qp_as<NMAX>(Wl, Ns_, lane, Dg, gi, ui, li, p.umin, p.umax, 8,
-                                                 d, nl, nu);
-                        ases += r.iters;
-                    }
-                    if (r.status == 2) {
-                        r = coop_box_qp<NMAX>(Wl, Ns_, lane, Dg, gi, ui, p.umin, p.umax,
-                                              p.ipm_max_iter, d, nl, nu);
-                        its += r.iters;
-                    }
-                    if (r.status != -1) break;
-                }
-                if (lane == s) {
-                    cnt[C_IPM] += its;
-                    cnt[C_AS] += ases;
-                    cnt[C_SQP]++;
-                    if (r.status == 1) cnt[C_IPMCAP]++;
-                }
-                if (in) {
-                    TB[(V_D * NMAX + lane) * 64 + s] = d;
-                    TB[(V_NL * NMAX + lane) * 64 + s] = nl;
-                    TB[(V_NU * NMAX + lane) * 64 + s] = nu;
-                }
-                __syncthreads();
+            const int flags = (int)((mp >> s) & 1ull) | ((int)((ma >> s) & 1ull) << 1);
+            const VisitOut vo =
+                p.qp_solver == 2
+                    ? coop_visit_h<NMAX>(TB, Ws, (lds_double*)Wl, Ns_, s, flags, p.umin, p.umax,
+                                         p.ipm_max_iter)
+                    : coop_visit_w<NMAX>(TB, Ws, (lds_double*)Wl, Ns_, s, flags, p.umin, p.umax,
+                                         p.ipm_max_iter, p.qp_solver);
+            if (lane == s) {
+                qfl += vo.fl;
+                cnt[C_SKIP] += vo.skip;
+                cnt[C_RESET] += vo.reset;
+                cnt[C_IPM] += vo.ipm;
+                cnt[C_AS] += vo.as;
+                cnt[C_SQP] += vo.sqp;
+                cnt[C_IPMCAP] += vo.ipmcap;
             }
         }
         pending = false;
@@ -257,6 +433,7 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
                 U[k * 64] = un;
                 PIL[k * 64] = PIL[k * 64] + alpha * (NLv[k * 64] - PIL[k * 64]);
                 PIU[k * 64] = PIU[k * 64] + alpha * (NUv[k * 64] - PIU[k * 64]);
+                Vv[k * 64] = alpha * Vv[k * 64];
             }
             if (GMODE == 1) ocp_grad_adjoint(p, N, i, su.istep, su.sign, U, Xs, G, Yv);
             else ocp_grad_fwd<NMAX>(p, N, i, su.istep, su.sign, U, Xs, G, Yv, Dv);
@@ -270,8 +447,7 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
 
 template <int NMAX, int GMODE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVES_PER_EU))) void nmpc_kernel(DevParams p, NmpcWork wk, Outs out) {
-    __shared__ double lds[5 * 64];
-    __shared__ __attribute__((aligned(16))) double Wl[NMAX * NMAX];   // staged W of one sample
+    __shared__ __attribute__((aligned(16))) double Wl[NMAX * NMAX];   // staged W (or H) of one sample
     const int lane = threadIdx.x;
     double* const TB = wk.tiles + (int64_t)blockIdx.x * wk.tile_stride;
     double* const XS = wk.xs + (int64_t)blockIdx.x * wk.xs_stride;
@@ -295,6 +471,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
         int cnt[C_NCNT];
 #pragma unroll
         for (int c = 0; c < C_NCNT; ++c) cnt[c] = 0;
+        double qfl = 0.0;   // inverse-form QP / BFGS / shift work of this lane's sample
         double n[3] = {su.n0[0], su.n0[1], su.n0[2]};
         double xhat = su.xhat0, P = p.P0, Fprev = su.ubar, phiacc = 0.0;
         uint64_t hsh = 14695981039346656037ull;
@@ -321,7 +498,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
                 if (!isfinite(xhat) || !isfinite(P)) cnt[C_NONFIN] = 1;
             }
             const bool conv = sqp_group<NMAX, GMODE>(p, step, N, i, su, xhat, lane, TB, XS, Wslot,
-                                                     Wl, lds, cnt);
+                                                     Wl, cnt, qfl);
             if (p.hess_warm) {
                 uint64_t m = __ballot(step);
                 while (m) {
@@ -329,8 +506,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
                     m &= m - 1;
                     const int Ns_ = __builtin_amdgcn_readlane(N, s);
                     double* Ws = Wslot + (int64_t)s * NMAX * NMAX;
-                    coop_stage<NMAX>(Ws, Wl, lane);
-                    coop_shift<NMAX>(Wl, Ws, Ns_, lane);
+                    const double fl =
+                        coop_visit_shift<NMAX>(TB, Ws, (lds_double*)Wl, Ns_, s, p.qp_solver == 2);
+                    if (lane == s) qfl += fl;
                 }
             }
             if (step) {
@@ -344,8 +522,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
                 }
                 hsh = fnv1a_step(hsh, (uint32_t)i, mask);
                 const double F = U[0] / kMlMinPerLs;
+                double* const WDv = TB + (V_WD * NMAX) * 64 + lane;
                 #pragma unroll 1
-                for (int k = 0; k + 1 < N; ++k) U[k * 64] = U[(k + 1) * 64];
+                for (int k = 0; k + 1 < N; ++k) {
+                    U[k * 64] = U[(k + 1) * 64];
+                    WDv[k * 64] = WDv[(k + 1) * 64];
+                }
                 if (out.tu) out.tu[(int64_t)i * out.S + pos] = F;
                 #pragma unroll 1
                 for (int j = 0; j < p.Ns; ++j) {
@@ -363,7 +545,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
             cnt[C_KIND] = 0;
             cnt[C_N] = N;
             cnt[C_L] = L;
-            out.flops[pos] = sample_flops(p, 0, N, L, cnt, GMODE);
+            out.flops[pos] = sample_flops(p, 0, N, L, cnt, GMODE, qfl);
 #pragma unroll
             for (int c = 0; c < C_NCNT; ++c) out.cnt[(int64_t)c * out.S + pos] = cnt[c];
         }
@@ -427,7 +609,7 @@ __global__ __launch_bounds__(64) void pi_kernel(DevParams p, const int64_t* pos_
     out.phi[pos] = phiacc / (double)(su.L + 1);
     out.hash[pos] = 14695981039346656037ull;
     const int vals[C_NCNT] = {1, su.N, su.L, 0, 0, 0, 0, 0, 0, 0, 0, 0, nonfin, 0, 0};
-    out.flops[pos] = sample_flops(p, 1, su.N, su.L, vals, 1);
+    out.flops[pos] = sample_flops(p, 1, su.N, su.L, vals, 1, 0.0);
 #pragma unroll
     for (int c = 0; c < C_NCNT; ++c) out.cnt[(int64_t)c * out.S + pos] = vals[c];
 }

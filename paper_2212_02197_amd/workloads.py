@@ -49,7 +49,7 @@ BASE = dict(
     sample_id_offset=0,            # first sample id (chunks, subsets)
     ckpt_interval=0,               # PI reverse pass checkpoint spacing (0: library default)
     samples_per_wave=0,            # NMPC lanes per wavefront (0: library plan)
-    qp_solver=1,                   # 1 active set (+ interior-point fallback), 0 interior point
+    qp_solver=2,                   # 2 inverse form, 1 active set on W, 0 interior point on W
 )
 
 
