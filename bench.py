@@ -36,7 +36,39 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the adjoint-vs-plain comparison")
     ap.add_argument("--plain-samples", type=int, default=3000)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run a plain elementwise copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
+
+
+def kernel_source_sha256():
+    """Hash of the kernel sources (csrc/*.hpp, csrc/*.hip sorted by name)."""
+    import glob
+    import hashlib
+    d = os.path.join(ROOT, "paper_2212_02197_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(d, "*.hpp")) + glob.glob(os.path.join(d, "*.hip"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per NMPC launch from the committed counter summary, or None
+    when the kernel sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "nmpc_kernel_c1_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) == 2 and parts[0] in ("source_sha256", "traffic_bytes_per_launch"):
+                vals[parts[0]] = parts[1]
+    if vals.get("source_sha256") != kernel_source_sha256() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(cfg, seconds):
@@ -71,6 +103,14 @@ def main():
 
     from paper_2212_02197_amd import binding, workloads
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", 0)))
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)   # reads and writes n * 8 bytes
+        torch.cuda.synchronize()
+        log(f"copy calibration: {n * 8} bytes read and written")
+        del a, b
     cfg = workloads.CONFIGS[args.config]()
     if args.samples:
         cfg["n_samples"] = args.samples
@@ -111,7 +151,8 @@ def main():
         achieved = nmpc_flops / (nmpc_ms / 1000.0) / 1e12
         roofline = dict(bound="alu", achieved=round(achieved, 4),
                         peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                        frac=round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5), traffic=None)
+                        frac=round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5),
+                        traffic=measured_traffic() if args.config == "c1" and not args.samples else None)
     camp_flops = stats["flops_algorithmic"]
     camp.close()
 
