@@ -341,7 +341,7 @@ int mc_cl_create(const mc_cl_params* p, mc_cl_ctx** out) {
         nc.groups = (int)((nc.count + nc.spw - 1) / nc.spw);
         nc.slots = std::min(nc.groups, slots_full);
         nc.tile_stride = (int64_t)V_COUNT * nc.nmax * 64;
-        nc.xs_stride = ((int64_t)nc.nmax * p->Nc * 4 + 1) * 64;
+        nc.xs_stride = (int64_t)3 * nc.nmax * 64;
         nc.w_stride = (int64_t)nc.spw * nc.nmax * nc.nmax;
         if ((rc = c->alloc(&nc.d_pos, nc.count)) ||
             (rc = c->alloc(&nc.d_tiles, (size_t)nc.slots * nc.tile_stride)) ||

@@ -701,6 +701,11 @@ __device__ __forceinline__ QPResult coop_box_qp_h(const double* Hl, lds_double* 
             ok = so.ok;
             lam = so.lam;
             xc = so.xc;
+            if (!ok) {
+                res.status = -1;
+                res.iters = it + 1;
+                return res;
+            }
             uint64_t mm = amask;
             #pragma unroll 1
             for (int k = 0; k < m; ++k) {

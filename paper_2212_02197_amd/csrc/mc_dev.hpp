@@ -204,7 +204,10 @@ struct Setup {
     double n0[3], xhat0, ubar;  // ubar in L/s
 };
 
-__device__ __forceinline__ Setup sample_setup(const DevParams& p, int64_t sid) {
+// Not inlined: it runs once per sample, and keeping its many loop-invariant
+// constants out of the persistent kernel's register allocation leaves that
+// allocation to the closed loop.
+__device__ __noinline__ Setup sample_setup(const DevParams& p, int64_t sid) {
     Setup s;
     const int64_t nid = p.noise_mod > 0 ? sid % p.noise_mod : sid;
     s.nid = (uint32_t)nid;
@@ -260,105 +263,123 @@ __device__ __forceinline__ Setup sample_setup(const DevParams& p, int64_t sid) {
 
 // ---------------------------------------------------- single shooting ---
 // Lane-tiled vectors: element k of the lane's sample at t[k * kTile].
-// Objective of the OCP at u + alpha d (d ignored when use_d is false).  The
-// trajectory goes to xs: for RK4 step m (m = k Nc + c) its start state and
-// first three stage slopes at xs[(4 m + 0..3) kTile], the final state at
-// xs[4 N Nc kTile]; the gradient sweeps then evaluate the four stage
-// derivatives of a step independently of each other.
+// Objective of the OCP at u + alpha d (d ignored when use_d is false).
+//
+// With kRec the pass also records, for every control interval k, what the
+// adjoint sweep needs, so that the sweep evaluates no model function and
+// reads 3 values per interval instead of a per-step tape:
+//   rec[(3 k + 0) kTile] = A_k = dx_{k+1}/dx_k,
+//   rec[(3 k + 1) kTile] = B_k = dx_{k+1}/du_k (per mL/min),
+//   rec[(3 k + 2) kTile] = c_k = d(stage cost at x_{k+1})/dx_{k+1}.
+// A_k and B_k are the derivatives of the interval's RK4^{Nc} map, carried
+// forward through the stages with df1/dx and df1/dF (which share f1's
+// exponential and division); they sit beside the state recursion, not on it.
+template <bool kRec>
 __device__ __forceinline__ double ocp_shoot(const DevParams& p, int N, double x0, int i0,
                                             int istep, double sign, const double* u,
                                             const double* d, double alpha, bool use_d,
-                                            double* xs) {
+                                            double* rec) {
     const double h = p.Ts / (double)p.Nc;
+    const double h2 = 0.5 * h, h6 = h / 6.0;
     const double iV = 1.0 / p.V;
     double x = x0, phi = 0.0;
-    int m = 0;
+    double un = u[0], dn = use_d ? d[0] : 0.0;   // interval k's input, loaded one interval ahead
 #pragma unroll 1
     for (int k = 0; k < N; ++k) {
-        double uk = u[k * kTile];
-        if (use_d) uk = uk + alpha * d[k * kTile];
+        double uk = un;
+        if (use_d) uk = uk + alpha * dn;
+        if (k + 1 < N) {
+            un = u[(k + 1) * kTile];
+            if (use_d) dn = d[(k + 1) * kTile];
+        }
         const double F = uk / kMlMinPerLs;
+        double A = 1.0, B = 0.0;
 #pragma unroll 1
-        for (int c = 0; c < p.Nc; ++c, ++m) {
-            const double k1 = model_f1(p, x, F);
-            const double k2 = model_f1(p, x + 0.5 * h * k1, F);
-            const double k3 = model_f1(p, x + 0.5 * h * k2, F);
-            const double k4 = model_f1(p, x + h * k3, F);
-            xs[(4 * m + 0) * kTile] = x;
-            xs[(4 * m + 1) * kTile] = k1;
-            xs[(4 * m + 2) * kTile] = k2;
-            xs[(4 * m + 3) * kTile] = k3;
-            x = x + h / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4);
+        for (int c = 0; c < p.Nc; ++c) {
+            if (kRec) {
+                double a0, a1, a2, a3, b0, b1, b2, b3;
+                const double k1 = model_f1<true>(p, x, F, a0, b0);
+                const double k2 = model_f1<true>(p, x + h2 * k1, F, a1, b1);
+                const double k3 = model_f1<true>(p, x + h2 * k2, F, a2, b2);
+                const double k4 = model_f1<true>(p, x + h * k3, F, a3, b3);
+                // derivatives of the step's stages w.r.t. its start state
+                const double t2 = a1 * (1.0 + h2 * a0);
+                const double t3 = a2 * (1.0 + h2 * t2);
+                const double t4 = a3 * (1.0 + h * t3);
+                const double Am = 1.0 + h6 * (a0 + 2.0 * t2 + 2.0 * t3 + t4);
+                // ... and w.r.t. F
+                const double s2 = b1 + a1 * h2 * b0;
+                const double s3 = b2 + a2 * h2 * s2;
+                const double s4 = b3 + a3 * h * s3;
+                const double Bm = h6 * (b0 + 2.0 * s2 + 2.0 * s3 + s4);
+                B = Am * B + Bm;
+                A = Am * A;
+                x = x + h6 * (k1 + 2.0 * k2 + 2.0 * k3 + k4);
+            } else {
+                const double k1 = model_f1(p, x, F);
+                const double k2 = model_f1(p, x + h2 * k1, F);
+                const double k3 = model_f1(p, x + h2 * k2, F);
+                const double k4 = model_f1(p, x + h * k3, F);
+                x = x + h6 * (k1 + 2.0 * k2 + 2.0 * k3 + k4);
+            }
         }
         const double ez = x * iV - setpoint(p, i0 + 1 + k, istep, sign);
         phi += p.Qz * ez * ez * p.Ts;
+        if (kRec) {
+            double* const r = rec + (int64_t)(3 * k) * kTile;
+            r[0] = A;
+            r[kTile] = B / kMlMinPerLs;
+            r[2 * kTile] = p.Qz * 2.0 * ez * iV * p.Ts;
+        }
     }
-    xs[(4 * m) * kTile] = x;
     return phi;
 }
 
-// Stage derivatives of RK4 step m from the stored trajectory:
-// a_s = df1/dx and b_s = df1/dF at the four stage arguments.
-__device__ __forceinline__ void rk4_stage_derivs(const DevParams& p, const double* xs, int m,
-                                                 double F, double h, double (&a)[4],
-                                                 double (&b)[4]) {
-    const double x = xs[(4 * m + 0) * kTile];
-    const double k1 = xs[(4 * m + 1) * kTile];
-    const double k2 = xs[(4 * m + 2) * kTile];
-    const double k3 = xs[(4 * m + 3) * kTile];
-    const double X[4] = {x, x + 0.5 * h * k1, x + 0.5 * h * k2, x + h * k3};
-#pragma unroll
-    for (int s = 0; s < 4; ++s) (void)model_f1<true>(p, X[s], F, a[s], b[s]);
-}
-
-// Discrete adjoint of the RK4 shooting: lambda runs back through every step.
-// Writes g[k] = dphi/du_k (mL/min) and, when y is given, y[k] = new - old
-// g[k] (the BFGS difference of the SQP).
-__device__ __forceinline__ void ocp_grad_adjoint(const DevParams& p, int N, int i0, int istep,
-                                                 double sign, const double* u, const double* xs,
-                                                 double* g, double* y) {
-    const double h = p.Ts / (double)p.Nc;
-    const double iV = 1.0 / p.V;
+// Discrete adjoint of the RK4 shooting over the recorded interval
+// derivatives: lambda_k = A_k (lambda_{k+1} + c_k), g_k = B_k (lambda_{k+1}
+// + c_k), backwards from lambda_N = 0.  Writes g[k] = dphi/du_k (mL/min)
+// and, when y is given, y[k] = new - old g[k] (the BFGS difference of the
+// SQP).  The records of 8 intervals are loaded together ahead of their use.
+__device__ __forceinline__ void ocp_grad_adjoint(int N, const double* rec, double* g, double* y) {
+    constexpr int kB = 8;
     double lam = 0.0;
 #pragma unroll 1
-    for (int k = N - 1; k >= 0; --k) {
-        const double F = u[k * kTile] / kMlMinPerLs;
-        double Fbar = 0.0;
-        {
-            const double xk1 = xs[(4 * (k + 1) * p.Nc) * kTile];
-            const double ez = xk1 * iV - setpoint(p, i0 + 1 + k, istep, sign);
-            lam += p.Qz * 2.0 * ez * iV * p.Ts;
+    for (int top = N - 1; top >= 0; top -= kB) {
+        double A[kB], Bv[kB], C[kB], G0[kB];
+#pragma unroll
+        for (int j = 0; j < kB; ++j) {
+            const int k = top - j >= 0 ? top - j : 0;
+            const double* const r = rec + (int64_t)(3 * k) * kTile;
+            A[j] = r[0];
+            Bv[j] = r[kTile];
+            C[j] = r[2 * kTile];
+            G0[j] = y ? g[k * kTile] : 0.0;
         }
-#pragma unroll 1
-        for (int c = p.Nc - 1; c >= 0; --c) {
-            double a[4], b[4];
-            rk4_stage_derivs(p, xs, k * p.Nc + c, F, h, a, b);
-            double xb = lam;
-            double kb1 = lam * h / 6.0, kb2 = lam * h / 3.0, kb3 = lam * h / 3.0;
-            const double kb4 = lam * h / 6.0;
-            xb += kb4 * a[3];  kb3 += kb4 * a[3] * h;        Fbar += kb4 * b[3];
-            xb += kb3 * a[2];  kb2 += kb3 * a[2] * 0.5 * h;  Fbar += kb3 * b[2];
-            xb += kb2 * a[1];  kb1 += kb2 * a[1] * 0.5 * h;  Fbar += kb2 * b[1];
-            xb += kb1 * a[0];                                Fbar += kb1 * b[0];
-            lam = xb;
+#pragma unroll
+        for (int j = 0; j < kB; ++j) {
+            const int k = top - j;
+            if (k >= 0) {
+                lam += C[j];
+                const double gk = Bv[j] * lam;
+                if (y) y[k * kTile] = gk - G0[j];
+                g[k * kTile] = gk;
+                lam = A[j] * lam;
+            }
         }
-        const double gk = Fbar / kMlMinPerLs;
-        if (y) {
-            y[k * kTile] = gk - g[k * kTile];
-        }
-        g[k * kTile] = gk;
     }
 }
 
-// Forward sensitivities: the tangent-linear RK4 carries dx/du_j for all
-// j <= k through each step (NMAX register slots, unrolled), with the stage
-// derivatives from the stored trajectory; dphi/du_j accumulates in the lane
-// tile `acc` (element j at acc[j * kTile]).
+// Plain forward sensitivities S_j = dx/du_j: the state is integrated again
+// from x0 with the inputs u, and the tangents of every u_j, j <= k, are
+// carried through each RK4 step with the stage derivatives (NMAX register
+// slots, unrolled); dphi/du_j accumulates in the lane tile `acc` (element j
+// at acc[j * kTile]).
 template <int NMAX>
-__device__ __forceinline__ void ocp_grad_fwd(const DevParams& p, int N, int i0, int istep,
-                                             double sign, const double* u, const double* xs,
-                                             double* g, double* y, double* acc) {
+__device__ __forceinline__ void ocp_grad_fwd(const DevParams& p, int N, double x0, int i0,
+                                             int istep, double sign, const double* u, double* g,
+                                             double* y, double* acc) {
     const double h = p.Ts / (double)p.Nc;
+    const double h2 = 0.5 * h, h6 = h / 6.0;
     const double iV = 1.0 / p.V;
     const double dF = 1.0 / kMlMinPerLs;
     double S[NMAX];
@@ -366,26 +387,30 @@ __device__ __forceinline__ void ocp_grad_fwd(const DevParams& p, int N, int i0, 
     for (int j = 0; j < NMAX; ++j) S[j] = 0.0;
 #pragma unroll 1
     for (int j = 0; j < N; ++j) acc[j * kTile] = 0.0;
+    double x = x0;
 #pragma unroll 1
     for (int k = 0; k < N; ++k) {
         const double F = u[k * kTile] / kMlMinPerLs;
 #pragma unroll 1
         for (int c = 0; c < p.Nc; ++c) {
             double a[4], b[4];
-            rk4_stage_derivs(p, xs, k * p.Nc + c, F, h, a, b);
+            const double k1 = model_f1<true>(p, x, F, a[0], b[0]);
+            const double k2 = model_f1<true>(p, x + h2 * k1, F, a[1], b[1]);
+            const double k3 = model_f1<true>(p, x + h2 * k2, F, a[2], b[2]);
+            const double k4 = model_f1<true>(p, x + h * k3, F, a[3], b[3]);
+            x = x + h6 * (k1 + 2.0 * k2 + 2.0 * k3 + k4);
 #pragma unroll
             for (int j = 0; j < NMAX; ++j) {
                 if (j <= k) {
                     const double src = (j == k) ? dF : 0.0;
                     const double d1 = a[0] * S[j] + b[0] * src;
-                    const double d2 = a[1] * (S[j] + 0.5 * h * d1) + b[1] * src;
-                    const double d3 = a[2] * (S[j] + 0.5 * h * d2) + b[2] * src;
+                    const double d2 = a[1] * (S[j] + h2 * d1) + b[1] * src;
+                    const double d3 = a[2] * (S[j] + h2 * d2) + b[2] * src;
                     const double d4 = a[3] * (S[j] + h * d3) + b[3] * src;
-                    S[j] = S[j] + h / 6.0 * (d1 + 2.0 * d2 + 2.0 * d3 + d4);
+                    S[j] = S[j] + h6 * (d1 + 2.0 * d2 + 2.0 * d3 + d4);
                 }
             }
         }
-        const double x = xs[(4 * (k + 1) * p.Nc) * kTile];
         const double ez = x * iV - setpoint(p, i0 + 1 + k, istep, sign);
         const double dphidx = p.Qz * 2.0 * ez * iV * p.Ts;
 #pragma unroll

@@ -50,7 +50,7 @@ struct NmpcWork {
     int n_groups;
     int* queue;
     double* tiles;       // per slot: V_COUNT * NMAX * 64
-    double* xs;          // per slot: (4 NMAX Nc + 1) * 64 (states and stage slopes)
+    double* xs;          // per slot: 3 NMAX * 64 (interval derivatives of the shooting)
     double* W;           // per slot: spw * NMAX * NMAX
     int64_t tile_stride, xs_stride, w_stride;
 };
@@ -72,8 +72,10 @@ __device__ __forceinline__ int wave_max_i(int v) {
 // Algorithmic FP64 work of one sample from its counters (each +, -, *, /,
 // sqrt, exp, log, sin, cos counts 1; an FMA counts 2; Philox is integer):
 //   cost term 3, measurement 8, EM sub-step with its noise 52, PI law 10,
-//   EKF interval 142 Nc + 12, shooting 73 N Nc + 9 N,
-//   adjoint gradient 142 N Nc + 7 N,
+//   EKF interval 142 Nc + 12, shooting 73 N Nc + 9 N per trial,
+//   adjoint gradient 78 N Nc + 9 N (the stage derivatives and interval
+//   Jacobians, counted once per gradient although the shooting pass records
+//   them at every trial, and the reverse sweep),
 //   forward-sensitivity gradient 117 N Nc + 13 Nc N (N+1) + N (N+1) + 6 N,
 //   interior-point iteration N^3/3 + 7 N^2 + 60 N,
 //   active-set iteration N^3/3 + 6 N^2 + 10 N,
@@ -91,7 +93,7 @@ __device__ __forceinline__ double sample_flops(const DevParams& p, int kind, int
     if (kind == 0 || p.run_ekf_for_pi) fl += l * (142.0 * Nc + 12.0);
     if (kind == 1) return fl + 10.0 * l;
     const double shoot = 73.0 * n * Nc + 9.0 * n;
-    const double grad = gmode == 1 ? 142.0 * n * Nc + 7.0 * n
+    const double grad = gmode == 1 ? 78.0 * n * Nc + 9.0 * n
                                    : 117.0 * n * Nc + 13.0 * Nc * n * (n + 1.0) + n * (n + 1.0) + 6.0 * n;
     const double ipm = n * n * n / 3.0 + 7.0 * n * n + 60.0 * n;
     const double asi = n * n * n / 3.0 + 6.0 * n * n + 10.0 * n;
@@ -329,7 +331,7 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
     double f = 0.0;
     if (live) {
         const bool fresh = i == 0 || !p.hess_warm;
-        #pragma unroll 1
+        #pragma unroll 4
         for (int k = 0; k < N; ++k) {
             double v = U[k * 64];
             if (v < p.umin) v = p.umin;
@@ -351,10 +353,10 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
         }
     }
     if (live) {
-        f = ocp_shoot(p, N, xhat, i, su.istep, su.sign, U, Dv, 0.0, false, Xs);
+        f = ocp_shoot<GMODE == 1>(p, N, xhat, i, su.istep, su.sign, U, Dv, 0.0, false, Xs);
         cnt[C_LS]++;
-        if (GMODE == 1) ocp_grad_adjoint(p, N, i, su.istep, su.sign, U, Xs, G, nullptr);
-        else ocp_grad_fwd<NMAX>(p, N, i, su.istep, su.sign, U, Xs, G, nullptr, Dv);
+        if (GMODE == 1) ocp_grad_adjoint(N, Xs, G, nullptr);
+        else ocp_grad_fwd<NMAX>(p, N, xhat, i, su.istep, su.sign, U, G, nullptr, Dv);
         cnt[C_GRAD]++;
     }
     bool active = live, pending = false, converged = false;
@@ -362,18 +364,21 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
     for (;;) {
         // scaled KKT test, eq. (convergence), on the lanes still iterating
         if (active) {
-            double s1 = 0.0;
-            #pragma unroll 1
-            for (int k = 0; k < N; ++k) s1 += fabs(PIL[k * 64]) + fabs(PIU[k * 64]);
-            const double sd = (s1 / (2.0 * N) > smax ? s1 / (2.0 * N) : smax) / smax;
-            double kkt = 0.0;
+            // one pass: s1 and the largest |grad L|_k (dividing by sd > 0
+            // afterwards selects the same maximum as dividing each term)
+            double s1 = 0.0, rmax = 0.0;
             bool bad = false;
-            #pragma unroll 1
+            #pragma unroll 4
             for (int k = 0; k < N; ++k) {
-                const double t = fabs(G[k * 64] - PIL[k * 64] + PIU[k * 64]) / sd;
-                bad |= (t != t);
-                kkt = t > kkt ? t : kkt;
+                const double pl = PIL[k * 64], pu = PIU[k * 64];
+                s1 += fabs(pl) + fabs(pu);
+                const double r = fabs(G[k * 64] - pl + pu);
+                bad |= (r != r);
+                rmax = r > rmax ? r : rmax;
             }
+            const double sd = (s1 / (2.0 * N) > smax ? s1 / (2.0 * N) : smax) / smax;
+            const double kkt = rmax / sd;
+            bad |= (kkt != kkt);
             if (!bad && kkt <= p.sqp_eps) { converged = true; active = false; }
             else if (l == p.sqp_max_iter) { active = false; }
         }
@@ -408,13 +413,14 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
         // backtracking line search, eq. (Armijo), one sample per lane
         double D = 0.0, alpha = 1.0;
         if (active)
-            #pragma unroll 1
+            #pragma unroll 4
             for (int k = 0; k < N; ++k) D += G[k * 64] * Dv[k * 64];
         bool searching = active;
         int bt = 0;
         while (__ballot(searching)) {
             if (searching) {
-                const double ft = ocp_shoot(p, N, xhat, i, su.istep, su.sign, U, Dv, alpha, true, Xs);
+                const double ft =
+                    ocp_shoot<GMODE == 1>(p, N, xhat, i, su.istep, su.sign, U, Dv, alpha, true, Xs);
                 cnt[C_LS]++;
                 bool accept = false;
                 if (bt == 0 && -D <= 64.0 * DBL_EPSILON * (1.0 + fabs(f))) accept = true;
@@ -425,7 +431,7 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
             }
         }
         if (active) {
-            #pragma unroll 1
+            #pragma unroll 4
             for (int k = 0; k < N; ++k) {
                 const double uo = U[k * 64];
                 const double un = uo + alpha * Dv[k * 64];
@@ -435,8 +441,8 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
                 PIU[k * 64] = PIU[k * 64] + alpha * (NUv[k * 64] - PIU[k * 64]);
                 Vv[k * 64] = alpha * Vv[k * 64];
             }
-            if (GMODE == 1) ocp_grad_adjoint(p, N, i, su.istep, su.sign, U, Xs, G, Yv);
-            else ocp_grad_fwd<NMAX>(p, N, i, su.istep, su.sign, U, Xs, G, Yv, Dv);
+            if (GMODE == 1) ocp_grad_adjoint(N, Xs, G, Yv);
+            else ocp_grad_fwd<NMAX>(p, N, xhat, i, su.istep, su.sign, U, G, Yv, Dv);
             cnt[C_GRAD]++;
             pending = true;
             ++l;
@@ -515,7 +521,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
                 cnt[C_OCP]++;
                 if (!conv) cnt[C_OCP_FAIL]++;
                 uint64_t mask = 0;
-                #pragma unroll 1
+                #pragma unroll 4
                 for (int k = 0; k < N; ++k) {
                     const double v = U[k * 64];
                     if (v <= p.umin + 1e-6 || v >= p.umax - 1e-6) mask |= (1ull << k);
@@ -523,7 +529,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
                 hsh = fnv1a_step(hsh, (uint32_t)i, mask);
                 const double F = U[0] / kMlMinPerLs;
                 double* const WDv = TB + (V_WD * NMAX) * 64 + lane;
-                #pragma unroll 1
+                #pragma unroll 4
                 for (int k = 0; k + 1 < N; ++k) {
                     U[k * 64] = U[(k + 1) * 64];
                     WDv[k * 64] = WDv[(k + 1) * 64];

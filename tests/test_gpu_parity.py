@@ -115,8 +115,13 @@ def test_c1_nmpc_sampled_paper_horizon():
 
 
 def test_deterministic_runs_and_trajectories():
+    # The KKT test stops the SQP once the scaled stationarity residual is
+    # below eps; near that threshold two roundings of the same iteration can
+    # stop one step apart, which moves the applied input by about eps
+    # relative.  The element-wise trajectory comparison therefore runs at
+    # eps = 1e-9, where that step is far below the 1e-5 tolerance on u.
     cfg = W.c1_paper_scale(n_samples=2, kind_split=1, noise_mod=1, noise_scale=0.0, N=20,
-                           Ns=10)
+                           Ns=10, sqp_eps=1e-9)
     phi, stats, ps, tr = gpu_run(cfg, traj=True)
     for s in range(2):
         r = oracle.run_sample(cfg, s, traj=True)
