@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the adjoint-vs-plain comparison")
     ap.add_argument("--plain-samples", type=int, default=3000)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the planned launch shape (skip the measured tuning)")
+    ap.add_argument("--tune-intervals", type=int, default=6)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain elementwise copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -120,6 +123,11 @@ def main():
     S = cfg["n_samples"]
     camp = binding.Campaign(cfg)
     log(f"campaign {args.config}: {S} samples, launch plan {camp.plan()}")
+    tuning = None
+    if not args.no_tune:
+        # measured launch shape, chosen before (outside) the timed region
+        tuning = camp.tune(trial_intervals=args.tune_intervals)
+        log(f"tuned launch shape: {tuning}; plan {camp.plan()}")
     for w in range(args.warmup):
         camp.run()
         camp.costs()
@@ -186,6 +194,7 @@ def main():
         "phi": {"mean_nmpc": stats["mean"][0], "var_nmpc": stats["var"][0],
                 "mean_pi": stats["mean"][1], "var_pi": stats["var"][1]},
         "launch_plan": plan,
+        "launch_tuning": tuning,
         "adjoint_vs_plain": plain,
         "algorithmic_gflop_per_step": round(camp_flops / 1e9, 3),
     }

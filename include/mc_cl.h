@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define MC_CL_ABI_VERSION 1u
+#define MC_CL_ABI_VERSION 2u
 #define MC_CL_SPMAX 8        /* setpoint schedule levels                        */
 #define MC_CL_NMAX 64        /* largest NMPC horizon                            */
 #define MC_CL_NHIST 202      /* histogram: underflow, 200 bins, overflow        */
@@ -131,7 +131,14 @@ typedef struct {
      * All return the QP's unique minimiser; the SQP iterates are the same up
      * to rounding.                                                          */
     int32_t qp_solver;
-    int32_t reserved0;
+    /* > 0: mc_cl_run processes the campaign in ceil(S / chunk_samples)
+     * chunks, each a contiguous range of every horizon class's wavefront
+     * groups and of the PI samples, by replaying one captured HIP graph of
+     * the chunk step (the NMPC and PI launches) per chunk with the chunk
+     * index kept on the device; 0: one launch per kernel.  Results are
+     * bitwise the same either way.  Trajectory outputs need chunk_samples =
+     * 0 (EUNSUPPORTED otherwise).                                           */
+    int32_t chunk_samples;
 } mc_cl_params;
 
 /* Optional outputs of mc_cl_run; every pointer may be NULL.  All are device
@@ -207,6 +214,31 @@ uint32_t mc_cl_abi_version(void);
  * returns the number of classes written (<= max_classes).                   */
 int mc_cl_kernel_ms(mc_cl_ctx *c, float ms[4]);
 int mc_cl_plan(mc_cl_ctx *c, int32_t *out, int max_classes);
+
+/* Measured launch-shape tuning (the batching runtime).  For every NMPC
+ * horizon class, times the campaign's own samples cut to their first
+ * `trial_intervals` closed-loop intervals at each candidate number of
+ * samples per wavefront (4, 8, 16, 32, 64) and keeps the fastest; for a
+ * campaign with want_grad and PI samples, times the PI forward pass with
+ * checkpoints plus the reverse pass at each candidate checkpoint interval
+ * C (10, 25, 50, 100, 200; those above the longest sample's L skipped,
+ * time -1) and keeps the fastest.  Phi and the counters are bitwise the
+ * same for every launch shape; C moves the gradient by rounding only (each
+ * segment is recomputed from its checkpoint).  Synchronises `hip_stream`; the trial launches overwrite the last
+ * run's results, so mc_cl_costs / mc_cl_grad need a new mc_cl_run.  The
+ * workspaces grow to the largest candidate tried.  EINVAL for a null
+ * argument or trial_intervals < 1; ENOMEM, EHIP.                           */
+#define MC_CL_TUNE_NSPW 5
+#define MC_CL_TUNE_NCK 5
+typedef struct {
+    int32_t n_classes;
+    int32_t nmax[3];                      /* NMAX of each horizon class      */
+    int32_t spw[3];                       /* chosen samples per wavefront    */
+    float nmpc_ms[3][MC_CL_TUNE_NSPW];    /* trial time per candidate        */
+    int32_t ckpt_interval;                /* chosen C (0: no PI gradient)    */
+    float grad_ms[MC_CL_TUNE_NCK];        /* trial time per candidate C      */
+} mc_cl_tune_result;
+int mc_cl_tune(mc_cl_ctx *c, void *hip_stream, int32_t trial_intervals, mc_cl_tune_result *r);
 
 #ifdef __cplusplus
 }

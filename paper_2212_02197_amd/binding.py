@@ -20,7 +20,7 @@ CNT_NAMES = ["kind", "N", "L", "n_ocp", "n_ocp_fail", "sqp_iter", "ipm_iter", "l
 NCNT = len(CNT_NAMES)
 STATUS = {0: "MC_CL_OK", -1: "MC_CL_EINVAL", -2: "MC_CL_EHIP", -3: "MC_CL_ENOMEM",
           -4: "MC_CL_ESTATE", -5: "MC_CL_EUNSUPPORTED"}
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 
 class Params(C.Structure):
@@ -51,7 +51,7 @@ class Params(C.Structure):
         ("hess_warm", C.c_int32), ("want_grad", C.c_int32),
         ("noise_scale", C.c_double),
         ("ckpt_interval", C.c_int32), ("samples_per_wave", C.c_int32),
-        ("qp_solver", C.c_int32), ("reserved0", C.c_int32),
+        ("qp_solver", C.c_int32), ("chunk_samples", C.c_int32),
     ]
 
 
@@ -67,8 +67,19 @@ class Stats(C.Structure):
                 ("workspace_bytes", C.c_size_t)]
 
 
+TUNE_SPW = (4, 8, 16, 32, 64)
+TUNE_CKPT = (10, 25, 50, 100, 200)
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("n_classes", C.c_int32), ("nmax", C.c_int32 * 3), ("spw", C.c_int32 * 3),
+                ("nmpc_ms", (C.c_float * len(TUNE_SPW)) * 3), ("ckpt_interval", C.c_int32),
+                ("grad_ms", C.c_float * len(TUNE_CKPT))]
+
+
 EXPORTS = ["mc_cl_create", "mc_cl_run", "mc_cl_costs", "mc_cl_grad", "mc_cl_destroy",
-           "mc_cl_strerror", "mc_cl_abi_version", "mc_cl_kernel_ms", "mc_cl_plan"]
+           "mc_cl_strerror", "mc_cl_abi_version", "mc_cl_kernel_ms", "mc_cl_plan",
+           "mc_cl_tune"]
 
 _lib = None
 
@@ -103,6 +114,8 @@ def lib():
         L.mc_cl_kernel_ms.argtypes = [vp, C.POINTER(C.c_float)]
         L.mc_cl_plan.restype = C.c_int
         L.mc_cl_plan.argtypes = [vp, C.POINTER(C.c_int32), C.c_int]
+        L.mc_cl_tune.restype = C.c_int
+        L.mc_cl_tune.argtypes = [vp, vp, C.c_int32, C.POINTER(TuneResult)]
         _lib = L
     return _lib
 
@@ -130,6 +143,7 @@ def params(cfg: dict) -> Params:
     p.ckpt_interval = cfg.get("ckpt_interval", 0)
     p.samples_per_wave = cfg.get("samples_per_wave", 0)
     p.qp_solver = cfg.get("qp_solver", 2)
+    p.chunk_samples = cfg.get("chunk_samples", 0)
     for a in range(3):
         p.sigma[a] = cfg["sigma"][a]
     sp_i, sp_z = cfg["sp_i"], cfg["sp_z"]
@@ -234,8 +248,70 @@ class Campaign:
         _check(lib().mc_cl_kernel_ms(self.h, ms), "mc_cl_kernel_ms")
         return list(ms)
 
+    def tune(self, trial_intervals: int = 6, stream=None):
+        """mc_cl_tune: measured samples-per-wavefront (and PI checkpoint
+        interval) choice; returns the trial times and the choice."""
+        st = stream if stream is not None else self.torch.cuda.current_stream()
+        r = TuneResult()
+        _check(lib().mc_cl_tune(self.h, C.c_void_p(st.cuda_stream), int(trial_intervals),
+                                C.byref(r)), "mc_cl_tune")
+        n = r.n_classes
+        return dict(
+            classes=[dict(nmax=r.nmax[k], spw=r.spw[k],
+                          trial_ms={s: round(float(r.nmpc_ms[k][j]), 3)
+                                    for j, s in enumerate(TUNE_SPW)}) for k in range(n)],
+            ckpt_interval=r.ckpt_interval,
+            grad_trial_ms={c: round(float(r.grad_ms[j]), 3) for j, c in enumerate(TUNE_CKPT)})
+
     def plan(self):
         buf = (C.c_int32 * 15)()
         n = lib().mc_cl_plan(self.h, buf, 3)
         return [dict(nmax=buf[5 * k], count=buf[5 * k + 1], spw=buf[5 * k + 2],
                      groups=buf[5 * k + 3], slots=buf[5 * k + 4]) for k in range(n)]
+
+
+def _pi_closed_loop_function():
+    import torch
+
+    class PIClosedLoop(torch.autograd.Function):
+        """Per-sample closed-loop cost Phi as a differentiable function of the PI
+        tuning theta = (Kc, tau_i), with kP = Kc and kI = Kc / tau_i (eq. (PI)).
+
+        forward runs the campaign on the HIP path with plant-state checkpoints
+        every `ckpt_interval` intervals (mc_cl_run with want_grad); backward
+        runs the reverse pass over those checkpoints (mc_cl_grad) and returns
+        sum_s grad_s dPhi_s/dtheta.  NMPC samples of a mixed campaign carry no
+        gradient.  theta: float64 tensor of shape (2,); returns Phi, shape (S,),
+        on the current device.
+        """
+
+        @staticmethod
+        def forward(ctx, theta, cfg):
+            Kc, taui = float(theta[0]), float(theta[1])
+            camp = Campaign(dict(cfg, kP=Kc, kI=Kc / taui, want_grad=1))
+            camp.run()
+            ctx.camp = camp
+            return camp.phi.clone()
+
+        @staticmethod
+        def backward(ctx, gout):
+            camp = ctx.camp
+            _, ps = camp.grad(per_sample=True)
+            camp.close()
+            ctx.camp = None
+            g = ps @ gout.to(ps.dtype)
+            return g.to(gout.device), None
+
+    return PIClosedLoop
+
+
+_PI_FN = None
+
+
+def pi_closed_loop(theta, cfg):
+    """Phi per sample at the PI tuning theta = (Kc, tau_i); differentiable in
+    theta through the library's reverse pass (see PIClosedLoop)."""
+    global _PI_FN
+    if _PI_FN is None:
+        _PI_FN = _pi_closed_loop_function()
+    return _PI_FN.apply(theta, cfg)

@@ -52,15 +52,34 @@ __global__ void fill_u64(unsigned long long* a, int n) {
     if (t < n) a[t] = 0ull;
 }
 
+// Chunked runs: ctl[0] is the chunk index c; ctl[1 + k] the end of class
+// k's groups in chunk c, whose work queue restarts at its first group.
+struct ChunkPlan {
+    int n_classes;
+    int gpc[3], groups[3];
+};
+__global__ void chunk_begin(int* ctl, int* queue, ChunkPlan cp) {
+    const int k = threadIdx.x;
+    if (k >= cp.n_classes) return;
+    const long long c = ctl[0];
+    const long long lo = c * cp.gpc[k], hi = lo + cp.gpc[k];
+    queue[k] = (int)(lo < cp.groups[k] ? lo : cp.groups[k]);
+    ctl[1 + k] = (int)(hi < cp.groups[k] ? hi : cp.groups[k]);
+}
+__global__ void chunk_end(int* ctl) {
+    if (threadIdx.x == 0) ctl[0] += 1;
+}
+
 struct NmpcClass {
     int nmax = 0;
     int64_t count = 0;
-    int spw = 64, groups = 0, slots = 0;
+    int spw = 64, groups = 0, slots = 0, slots_full = 0;
     int64_t* d_pos = nullptr;
     double* d_tiles = nullptr;
     double* d_xs = nullptr;
     double* d_W = nullptr;
     int64_t tile_stride = 0, xs_stride = 0, w_stride = 0;
+    size_t cap_tiles = 0, cap_xs = 0, cap_W = 0;   // allocated elements
 };
 
 template <int NMAX, int GMODE>
@@ -116,6 +135,13 @@ struct mc_cl_ctx {
     bool uniform_L = true;
     std::vector<NmpcClass> classes;
     int* d_queue = nullptr;   // one counter per class
+    int* d_ctl = nullptr;     // chunked runs: chunk index, group ends per class
+    int n_chunks = 1;
+    int64_t pi_per_chunk = 0;
+    ChunkPlan cplan{};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int Lmax = 0;
     int64_t* d_pos_pi = nullptr;
     double* d_phi = nullptr;
     double* d_flops = nullptr;
@@ -138,6 +164,8 @@ struct mc_cl_ctx {
     size_t bytes = 0;
     std::vector<void*> allocs;
 
+    std::vector<size_t> alloc_bytes;
+
     template <class T>
     int alloc(T** p, size_t n) {
         *p = nullptr;
@@ -145,13 +173,35 @@ struct mc_cl_ctx {
         void* v = nullptr;
         HIPCHK(hipMalloc(&v, n * sizeof(T)));
         allocs.push_back(v);
+        alloc_bytes.push_back(n * sizeof(T));
         bytes += n * sizeof(T);
         *p = (T*)v;
         return MC_CL_OK;
     }
+    // Free *p (if the context owns it) and allocate n elements instead.
+    template <class T>
+    int realloc_dev(T** p, size_t n) {
+        for (size_t k = 0; k < allocs.size(); ++k) {
+            if (allocs[k] == (void*)*p && *p) {
+                HIPCHK(hipFree(allocs[k]));
+                bytes -= alloc_bytes[k];
+                allocs.erase(allocs.begin() + k);
+                alloc_bytes.erase(alloc_bytes.begin() + k);
+                break;
+            }
+        }
+        return alloc(p, n);
+    }
+    void drop_graph() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+    }
     ~mc_cl_ctx() {
         (void)hipSetDevice(device);
         (void)hipDeviceSynchronize();
+        drop_graph();
         for (void* v : allocs) (void)hipFree(v);
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -197,9 +247,131 @@ static int validate(const mc_cl_params* p) {
     if (p->ckpt_interval < 0 || p->samples_per_wave < 0 || p->samples_per_wave > 64)
         return MC_CL_EINVAL;
     if (p->qp_solver < 0 || p->qp_solver > 2) return MC_CL_EINVAL;
+    if (p->chunk_samples < 0) return MC_CL_EINVAL;
     if (p->sample_id_offset < 0 || p->sample_id_offset + p->n_samples > (int64_t)UINT32_MAX)
         return MC_CL_EINVAL;
     return MC_CL_OK;
+}
+
+// Launch shape of an NMPC class for `spw` samples per wavefront; grows the
+// class's wave-slot workspaces when the shape needs more of them.
+static int plan_class(mc_cl_ctx* c, NmpcClass& nc, int spw) {
+    nc.spw = spw;
+    nc.groups = (int)((nc.count + spw - 1) / spw);
+    nc.slots = std::min(nc.groups, nc.slots_full);
+    nc.tile_stride = (int64_t)V_COUNT * nc.nmax * 64;
+    nc.xs_stride = (int64_t)3 * nc.nmax * 64;
+    nc.w_stride = (int64_t)spw * nc.nmax * nc.nmax;
+    const size_t nt = (size_t)nc.slots * nc.tile_stride;
+    const size_t nx = (size_t)nc.slots * nc.xs_stride;
+    const size_t nw = (size_t)nc.slots * nc.w_stride;
+    int rc;
+    if (nt > nc.cap_tiles) {
+        if ((rc = c->realloc_dev(&nc.d_tiles, nt))) return rc;
+        nc.cap_tiles = nt;
+    }
+    if (nx > nc.cap_xs) {
+        if ((rc = c->realloc_dev(&nc.d_xs, nx))) return rc;
+        nc.cap_xs = nx;
+    }
+    if (nw > nc.cap_W) {
+        if ((rc = c->realloc_dev(&nc.d_W, nw))) return rc;
+        nc.cap_W = nw;
+        HIPCHK(hipMemset(nc.d_W, 0, nw * 8));
+    }
+    return MC_CL_OK;
+}
+
+// PI reverse-pass buffers for checkpoints every C intervals: the plant
+// states at the segment starts, and one segment's sub-step and interval
+// tapes.
+static int size_ckpt(mc_cl_ctx* c, int C) {
+    const int64_t nseg = std::max<int64_t>((c->Lmax + C - 1) / C, 1);
+    int rc;
+    if ((rc = c->realloc_dev(&c->d_ck, (size_t)nseg * 4 * c->n_pi)) ||
+        (rc = c->realloc_dev(&c->d_tape, (size_t)C * c->prm.Ns * 6 * c->n_pi)) ||
+        (rc = c->realloc_dev(&c->d_ivtape, (size_t)C * 5 * c->n_pi)))
+        return rc;
+    c->ckC = C;
+    c->dp.ckpt_C = C;
+    return MC_CL_OK;
+}
+
+// Work of each chunk: a contiguous range of every class's groups and of
+// the PI samples.
+static void set_chunk_plan(mc_cl_ctx* c) {
+    const int nch = std::max(c->n_chunks, 1);
+    c->cplan.n_classes = (int)c->classes.size();
+    for (size_t k = 0; k < c->classes.size(); ++k) {
+        c->cplan.groups[k] = c->classes[k].groups;
+        c->cplan.gpc[k] = (c->classes[k].groups + nch - 1) / nch;
+    }
+    c->pi_per_chunk = (c->n_pi + nch - 1) / nch;
+}
+
+// One campaign step on `st`: every NMPC class's persistent launch, then the
+// PI launch.  With chunk set the step covers chunk ctl[0] only and ends by
+// advancing it (the sequence captured in the run graph).  `ev_mid` (or
+// null) is recorded between the NMPC and PI launches.
+static int launch_step(mc_cl_ctx* c, hipStream_t st, const Outs& out, bool chunk,
+                       hipEvent_t ev_mid) {
+    if (chunk) {
+        hipLaunchKernelGGL(chunk_begin, dim3(1), dim3(64), 0, st, c->d_ctl, c->d_queue, c->cplan);
+        HIPCHK(hipGetLastError());
+    } else {
+        hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, c->d_queue, 4, 0);
+        HIPCHK(hipGetLastError());
+    }
+    for (size_t k = 0; k < c->classes.size(); ++k) {
+        const NmpcClass& nc = c->classes[k];
+        NmpcWork wk{nc.d_pos, nc.count, nc.spw, nc.groups, c->d_queue + k,
+                    chunk ? c->d_ctl + 1 + k : nullptr, nc.d_tiles, nc.d_xs, nc.d_W,
+                    nc.tile_stride, nc.xs_stride, nc.w_stride};
+        HIPCHK(dispatch_nmpc(nc.nmax, c->prm.grad_mode, c->dp, wk, out, nc.slots, st));
+    }
+    if (ev_mid) HIPCHK(hipEventRecord(ev_mid, st));
+    if (c->n_pi) {
+        const int64_t n = chunk ? c->pi_per_chunk : c->n_pi;
+        hipLaunchKernelGGL(pi_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, c->dp,
+                           c->d_pos_pi, c->n_pi, out, c->d_ck, chunk ? c->d_ctl : nullptr,
+                           c->pi_per_chunk);
+        HIPCHK(hipGetLastError());
+    }
+    if (chunk) {
+        hipLaunchKernelGGL(chunk_end, dim3(1), dim3(64), 0, st, c->d_ctl);
+        HIPCHK(hipGetLastError());
+    }
+    return MC_CL_OK;
+}
+
+// Capture one chunk step into a graph and instantiate it.
+static int capture_step(mc_cl_ctx* c, const Outs& out) {
+    hipStream_t cs = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    int rc = MC_CL_OK;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        g_hip_error = "hipStreamBeginCapture failed";
+        rc = MC_CL_EHIP;
+    } else {
+        rc = launch_step(c, cs, out, true, nullptr);
+        const hipError_t e = hipStreamEndCapture(cs, &g);
+        if (rc == MC_CL_OK && e != hipSuccess) {
+            g_hip_error = std::string("hipStreamEndCapture: ") + hipGetErrorString(e);
+            rc = MC_CL_EHIP;
+        }
+    }
+    if (rc == MC_CL_OK) {
+        const hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            g_hip_error = std::string("hipGraphInstantiate: ") + hipGetErrorString(e);
+            rc = MC_CL_EHIP;
+        }
+    }
+    if (rc == MC_CL_OK) c->graph = g;
+    else if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    return rc;
 }
 
 static DevParams to_dev(const mc_cl_params& p) {
@@ -227,6 +399,7 @@ static DevParams to_dev(const mc_cl_params& p) {
     d.hess_warm = p.hess_warm; d.want_grad = p.want_grad; d.noise_scale = p.noise_scale;
     d.ckpt_C = 0;
     d.qp_solver = p.qp_solver;
+    d.L_cap = INT32_MAX;
     return d;
 }
 
@@ -333,42 +506,31 @@ int mc_cl_create(const mc_cl_params* p, mc_cl_ctx** out) {
         nc.count = (int64_t)v.size();
         c->n_nmpc += nc.count;
         const int bpc = blocks_per_cu(nc.nmax, gmode);
-        const int slots_full = bpc * c->n_cu;
+        nc.slots_full = bpc * c->n_cu;
         int nmax_in_class = 1;
         for (int64_t q : v) nmax_in_class = std::max(nmax_in_class, Nv[q]);
-        nc.spw = p->samples_per_wave > 0 ? p->samples_per_wave
-                                         : choose_spw(nc.count, nmax_in_class, slots_full);
-        nc.groups = (int)((nc.count + nc.spw - 1) / nc.spw);
-        nc.slots = std::min(nc.groups, slots_full);
-        nc.tile_stride = (int64_t)V_COUNT * nc.nmax * 64;
-        nc.xs_stride = (int64_t)3 * nc.nmax * 64;
-        nc.w_stride = (int64_t)nc.spw * nc.nmax * nc.nmax;
-        if ((rc = c->alloc(&nc.d_pos, nc.count)) ||
-            (rc = c->alloc(&nc.d_tiles, (size_t)nc.slots * nc.tile_stride)) ||
-            (rc = c->alloc(&nc.d_xs, (size_t)nc.slots * nc.xs_stride)) ||
-            (rc = c->alloc(&nc.d_W, (size_t)nc.slots * nc.w_stride)))
-            return fail(rc);
+        const int spw = p->samples_per_wave > 0 ? p->samples_per_wave
+                                                : choose_spw(nc.count, nmax_in_class, nc.slots_full);
+        if ((rc = c->alloc(&nc.d_pos, nc.count)) || (rc = plan_class(c, nc, spw))) return fail(rc);
         if (hipMemcpy(nc.d_pos, v.data(), nc.count * 8, hipMemcpyHostToDevice) != hipSuccess)
-            return fail(MC_CL_EHIP);
-        if (hipMemset(nc.d_W, 0, (size_t)nc.slots * nc.w_stride * 8) != hipSuccess)
             return fail(MC_CL_EHIP);
         c->classes.push_back(nc);
     }
-    if ((rc = c->alloc(&c->d_queue, 4)) || (rc = c->alloc(&c->d_phi, S)) ||
+    c->Lmax = Lmax;
+    if ((rc = c->alloc(&c->d_queue, 4)) || (rc = c->alloc(&c->d_ctl, 4)) ||
+        (rc = c->alloc(&c->d_phi, S)) ||
         (rc = c->alloc(&c->d_flops, S)) || (rc = c->alloc(&c->d_cnt, (size_t)C_NCNT * S)) ||
         (rc = c->alloc(&c->d_hash, S)) || (rc = c->alloc(&c->d_stats, 8)) ||
         (rc = c->alloc(&c->d_hist, 2 * MC_CL_NHIST)) || (rc = c->alloc(&c->d_totals, MC_CL_NCNT)))
         return fail(rc);
     if (p->want_grad && c->n_pi) {
-        c->ckC = p->ckpt_interval > 0 ? p->ckpt_interval : 50;
-        const int64_t nseg = (Lmax + c->ckC - 1) / c->ckC;
-        c->dp.ckpt_C = c->ckC;
-        if ((rc = c->alloc(&c->d_ck, (size_t)std::max<int64_t>(nseg, 1) * 4 * c->n_pi)) ||
-            (rc = c->alloc(&c->d_tape, (size_t)c->ckC * p->Ns * 6 * c->n_pi)) ||
-            (rc = c->alloc(&c->d_ivtape, (size_t)c->ckC * 5 * c->n_pi)) ||
+        if ((rc = size_ckpt(c, p->ckpt_interval > 0 ? p->ckpt_interval : 50)) ||
             (rc = c->alloc(&c->d_gk, (size_t)2 * c->n_pi)) || (rc = c->alloc(&c->d_gsum, 2)))
             return fail(rc);
     }
+    if (p->chunk_samples > 0)
+        c->n_chunks = (int)std::max<int64_t>(1, (S + p->chunk_samples - 1) / p->chunk_samples);
+    set_chunk_plan(c);
     for (auto& e : c->ev)
         if (hipEventCreate(&e) != hipSuccess) return fail(MC_CL_EHIP);
     *out = c;
@@ -377,29 +539,35 @@ int mc_cl_create(const mc_cl_params* p, mc_cl_ctx** out) {
 
 int mc_cl_run(mc_cl_ctx* c, void* hip_stream, const mc_cl_outputs* o) {
     if (!c) return MC_CL_EINVAL;
-    if (o && (o->traj_z || o->traj_u || o->traj_xhat) && !c->uniform_L) return MC_CL_ESTATE;
+    const bool traj = o && (o->traj_z || o->traj_u || o->traj_xhat);
+    if (traj && !c->uniform_L) return MC_CL_ESTATE;
+    const bool chunked = c->n_chunks > 1;
+    if (traj && chunked) return MC_CL_EUNSUPPORTED;
     HIPCHK(hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)hip_stream;
     Outs out{c->d_phi, c->d_flops, c->d_cnt, c->d_hash,
              o ? o->traj_z : nullptr, o ? o->traj_u : nullptr, o ? o->traj_xhat : nullptr, c->S};
-    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, c->d_queue, 4, 0);
     hipLaunchKernelGGL(fill_u64, dim3((2 * MC_CL_NHIST + MC_CL_NCNT + 255) / 256), dim3(256), 0,
                        st, c->d_hist, 2 * MC_CL_NHIST);
     hipLaunchKernelGGL(fill_u64, dim3(1), dim3(64), 0, st, (unsigned long long*)c->d_totals,
                        MC_CL_NCNT);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipEventRecord(c->ev[0], st));
-    for (size_t k = 0; k < c->classes.size(); ++k) {
-        const NmpcClass& nc = c->classes[k];
-        NmpcWork wk{nc.d_pos, nc.count, nc.spw, nc.groups, c->d_queue + k,
-                    nc.d_tiles, nc.d_xs, nc.d_W, nc.tile_stride, nc.xs_stride, nc.w_stride};
-        HIPCHK(dispatch_nmpc(nc.nmax, c->prm.grad_mode, c->dp, wk, out, nc.slots, st));
-    }
-    HIPCHK(hipEventRecord(c->ev[1], st));
-    if (c->n_pi) {
-        hipLaunchKernelGGL(pi_kernel, dim3((unsigned)((c->n_pi + 63) / 64)), dim3(64), 0, st, c->dp,
-                           c->d_pos_pi, c->n_pi, out, c->d_ck);
+    if (chunked) {
+        // the captured chunk step, replayed once per chunk; it starts from
+        // chunk 0 and advances the device-side chunk index itself
+        if (!c->gexec) {
+            const int rc = capture_step(c, out);
+            if (rc != MC_CL_OK) return rc;
+        }
+        hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, c->d_ctl, 4, 0);
         HIPCHK(hipGetLastError());
+        HIPCHK(hipEventRecord(c->ev[0], st));
+        for (int k = 0; k < c->n_chunks; ++k) HIPCHK(hipGraphLaunch(c->gexec, st));
+        HIPCHK(hipEventRecord(c->ev[1], st));
+    } else {
+        HIPCHK(hipEventRecord(c->ev[0], st));
+        const int rc = launch_step(c, st, out, false, c->ev[1]);
+        if (rc != MC_CL_OK) return rc;
     }
     HIPCHK(hipEventRecord(c->ev[2], st));
     hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(1024), 0, st, c->d_phi, c->d_cnt, c->S,
@@ -496,6 +664,102 @@ int mc_cl_kernel_ms(mc_cl_ctx* c, float ms[4]) {
     ms[3] = 0.0f;
     if (c->grad_ran) HIPCHK(hipEventElapsedTime(&ms[3], c->ev[4], c->ev[5]));
     return MC_CL_OK;
+}
+
+int mc_cl_tune(mc_cl_ctx* c, void* hip_stream, int32_t trial_intervals, mc_cl_tune_result* r) {
+    if (!c || !r || trial_intervals < 1) return MC_CL_EINVAL;
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::memset(r, 0, sizeof(*r));
+    static const int kSpw[MC_CL_TUNE_NSPW] = {4, 8, 16, 32, 64};
+    static const int kCk[MC_CL_TUNE_NCK] = {10, 25, 50, 100, 200};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        g_hip_error = "hipEventCreate failed";
+        return MC_CL_EHIP;
+    }
+    auto timed = [&](auto&& launches, float& ms) -> int {
+        HIPCHK(hipEventRecord(e0, st));
+        const int rc = launches();
+        if (rc != MC_CL_OK) return rc;
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        return MC_CL_OK;
+    };
+    int rc = MC_CL_OK;
+    // NMPC: the campaign's own samples, cut to the first trial_intervals
+    // intervals, for every candidate number of samples per wavefront
+    DevParams dt = c->dp;
+    dt.L_cap = trial_intervals;
+    const Outs out{c->d_phi, c->d_flops, c->d_cnt, c->d_hash, nullptr, nullptr, nullptr, c->S};
+    r->n_classes = (int32_t)c->classes.size();
+    for (size_t k = 0; k < c->classes.size() && rc == MC_CL_OK; ++k) {
+        NmpcClass& nc = c->classes[k];
+        r->nmax[k] = nc.nmax;
+        float best = INFINITY;
+        int bspw = nc.spw;
+        for (int j = 0; j < MC_CL_TUNE_NSPW && rc == MC_CL_OK; ++j) {
+            if ((rc = plan_class(c, nc, kSpw[j])) != MC_CL_OK) break;
+            float ms = 0.0f;
+            rc = timed([&]() -> int {
+                hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, c->d_queue + k, 1, 0);
+                HIPCHK(hipGetLastError());
+                NmpcWork wk{nc.d_pos, nc.count, nc.spw, nc.groups, c->d_queue + k, nullptr,
+                            nc.d_tiles, nc.d_xs, nc.d_W, nc.tile_stride, nc.xs_stride,
+                            nc.w_stride};
+                HIPCHK(dispatch_nmpc(nc.nmax, c->prm.grad_mode, dt, wk, out, nc.slots, st));
+                return MC_CL_OK;
+            }, ms);
+            r->nmpc_ms[k][j] = ms;
+            if (rc == MC_CL_OK && ms < best) {
+                best = ms;
+                bspw = kSpw[j];
+            }
+        }
+        if (rc == MC_CL_OK) rc = plan_class(c, nc, bspw);
+        r->spw[k] = nc.spw;
+    }
+    // PI gradient: forward pass with checkpoints plus reverse pass, whole
+    // campaign, for every candidate checkpoint interval up to the length
+    if (rc == MC_CL_OK && c->prm.want_grad && c->n_pi) {
+        float best = INFINITY;
+        int bC = c->ckC;
+        for (int j = 0; j < MC_CL_TUNE_NCK && rc == MC_CL_OK; ++j) {
+            r->grad_ms[j] = -1.0f;
+            if (j > 0 && kCk[j] > std::max(c->Lmax, 1)) continue;
+            if ((rc = size_ckpt(c, kCk[j])) != MC_CL_OK) break;
+            float ms = 0.0f;
+            rc = timed([&]() -> int {
+                const unsigned nb = (unsigned)((c->n_pi + 63) / 64);
+                hipLaunchKernelGGL(pi_kernel, dim3(nb), dim3(64), 0, st, c->dp, c->d_pos_pi,
+                                   c->n_pi, out, c->d_ck, nullptr, (int64_t)0);
+                HIPCHK(hipGetLastError());
+                hipLaunchKernelGGL(pi_reverse_kernel, dim3(nb), dim3(64), 0, st, c->dp,
+                                   c->d_pos_pi, c->n_pi, c->d_ck, c->d_tape, c->d_ivtape, c->d_gk);
+                HIPCHK(hipGetLastError());
+                return MC_CL_OK;
+            }, ms);
+            r->grad_ms[j] = ms;
+            if (rc == MC_CL_OK && ms < best) {
+                best = ms;
+                bC = kCk[j];
+            }
+        }
+        if (rc == MC_CL_OK) rc = size_ckpt(c, bC);
+        r->ckpt_interval = c->ckC;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // the trial launches overwrote the outputs; the run graph holds the old
+    // launch shape
+    c->drop_graph();
+    set_chunk_plan(c);
+    c->ran = false;
+    c->grad_ran = false;
+    return rc;
 }
 
 int mc_cl_plan(mc_cl_ctx* c, int32_t* out, int max_classes) {

@@ -39,6 +39,7 @@ struct DevParams {
     int hess_warm, want_grad;
     double noise_scale;
     int ckpt_C, qp_solver;
+    int L_cap;           // closed-loop intervals are cut at L_cap (trial launches)
 };
 
 // Noise streams: the counter's last word.
@@ -222,6 +223,7 @@ __device__ __noinline__ Setup sample_setup(const DevParams& p, int64_t sid) {
         const double u = philox_uniforms(p.seed, 1, 0, s.nid, kTagScen).u2;
         s.L = p.L_lo + (int)floor(u * (double)(p.L_hi - p.L_lo + 1));
     }
+    if (s.L > p.L_cap) s.L = p.L_cap;
     s.istep = 0;
     s.sign = 0.0;
     if (p.sp_step_rel != 0.0) {
@@ -335,49 +337,30 @@ __device__ __forceinline__ double ocp_shoot(const DevParams& p, int N, double x0
     return phi;
 }
 
-// Discrete adjoint of the RK4 shooting over the recorded interval
-// derivatives: lambda_k = A_k (lambda_{k+1} + c_k), g_k = B_k (lambda_{k+1}
-// + c_k), backwards from lambda_N = 0.  Writes g[k] = dphi/du_k (mL/min)
-// and, when y is given, y[k] = new - old g[k] (the BFGS difference of the
-// SQP).  The records of 8 intervals are loaded together ahead of their use.
-__device__ __forceinline__ void ocp_grad_adjoint(int N, const double* rec, double* g, double* y) {
-    constexpr int kB = 8;
-    double lam = 0.0;
-#pragma unroll 1
-    for (int top = N - 1; top >= 0; top -= kB) {
-        double A[kB], Bv[kB], C[kB], G0[kB];
-#pragma unroll
-        for (int j = 0; j < kB; ++j) {
-            const int k = top - j >= 0 ? top - j : 0;
-            const double* const r = rec + (int64_t)(3 * k) * kTile;
-            A[j] = r[0];
-            Bv[j] = r[kTile];
-            C[j] = r[2 * kTile];
-            G0[j] = y ? g[k * kTile] : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < kB; ++j) {
-            const int k = top - j;
-            if (k >= 0) {
-                lam += C[j];
-                const double gk = Bv[j] * lam;
-                if (y) y[k * kTile] = gk - G0[j];
-                g[k * kTile] = gk;
-                lam = A[j] * lam;
-            }
-        }
-    }
+// The sums of the scaled KKT test, eq. (convergence), over a lane's sample:
+// s1 = sum |pi_l| + |pi_u| and rmax = max |g - pi_l + pi_u| (bad: NaN seen).
+struct KktSums {
+    double s1, rmax;
+    bool bad;
+};
+__device__ __forceinline__ void kkt_add(KktSums& r, double g, double pl, double pu) {
+    r.s1 += fabs(pl) + fabs(pu);
+    const double v = fabs(g - pl + pu);
+    r.bad |= (v != v);
+    r.rmax = v > r.rmax ? v : r.rmax;
 }
 
 // Plain forward sensitivities S_j = dx/du_j: the state is integrated again
 // from x0 with the inputs u, and the tangents of every u_j, j <= k, are
 // carried through each RK4 step with the stage derivatives (NMAX register
 // slots, unrolled); dphi/du_j accumulates in the lane tile `acc` (element j
-// at acc[j * kTile]).
+// at acc[j * kTile]).  Returns the sums of the next KKT test with the
+// multipliers pil, piu.
 template <int NMAX>
-__device__ __forceinline__ void ocp_grad_fwd(const DevParams& p, int N, double x0, int i0,
-                                             int istep, double sign, const double* u, double* g,
-                                             double* y, double* acc) {
+__device__ __forceinline__ KktSums ocp_grad_fwd(const DevParams& p, int N, double x0, int i0,
+                                                int istep, double sign, const double* u,
+                                                double* g, double* y, double* acc,
+                                                const double* pil, const double* piu) {
     const double h = p.Ts / (double)p.Nc;
     const double h2 = 0.5 * h, h6 = h / 6.0;
     const double iV = 1.0 / p.V;
@@ -417,12 +400,15 @@ __device__ __forceinline__ void ocp_grad_fwd(const DevParams& p, int N, double x
         for (int j = 0; j < NMAX; ++j)
             if (j <= k) acc[j * kTile] += dphidx * S[j];
     }
+    KktSums r{0.0, 0.0, false};
 #pragma unroll 1
     for (int j = 0; j < N; ++j) {
         const double gj = acc[j * kTile];
         if (y) y[j * kTile] = gj - g[j * kTile];
         g[j * kTile] = gj;
+        kkt_add(r, gj, pil[j * kTile], piu[j * kTile]);
     }
+    return r;
 }
 
 }  // namespace mccl

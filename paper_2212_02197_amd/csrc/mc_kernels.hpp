@@ -48,7 +48,8 @@ struct NmpcWork {
     int64_t n_pos;
     int spw;
     int n_groups;
-    int* queue;
+    int* queue;          // next group; starts at the chunk's first group
+    const int* qhi;      // end of the chunk's groups (device), or null: n_groups
     double* tiles;       // per slot: V_COUNT * NMAX * 64
     double* xs;          // per slot: 3 NMAX * 64 (interval derivatives of the shooting)
     double* W;           // per slot: spw * NMAX * NMAX
@@ -115,6 +116,7 @@ __device__ __forceinline__ double sample_flops(const DevParams& p, int kind, int
 struct VisitOut {
     double fl;
     int skip, reset, ipm, as, sqp, ipmcap;
+    double gd;   // g'd of the QP step (the line search's directional derivative)
 };
 
 // H (or W) <- I in global memory and the staged copy: the rare reset after
@@ -161,7 +163,7 @@ __device__ __forceinline__ VisitOut coop_visit_h(double* TB, double* Ws, lds_dou
     flags = uni(flags);
     umin = uni_d(umin);
     umax = uni_d(umax);
-    VisitOut vo{0.0, 0, 0, 0, 0, 0, 0};
+    VisitOut vo{0.0, 0, 0, 0, 0, 0, 0, 0.0};
     const bool in = lane < Ns_;
     double* const wdp = TB + (V_WD * NMAX + lane) * 64 + s;
     // the sample's vectors (column s of the lane tiles) are loaded while H
@@ -211,6 +213,7 @@ __device__ __forceinline__ VisitOut coop_visit_h(double* TB, double* Ws, lds_dou
         }
         vo.sqp = 1;
         if (r.status == 1) vo.ipmcap = 1;
+        vo.gd = wave_sum(in ? gi * d : 0.0);
         if (in) {
             TB[(V_D * NMAX + lane) * 64 + s] = d;
             TB[(V_NL * NMAX + lane) * 64 + s] = nl;
@@ -239,7 +242,7 @@ __device__ __noinline__ VisitOut coop_visit_w(double* TB, double* Ws, lds_double
     ipm_max_iter = uni(ipm_max_iter);
     umin = uni_d(umin);
     umax = uni_d(umax);
-    VisitOut vo{0.0, 0, 0, 0, 0, 0, 0};
+    VisitOut vo{0.0, 0, 0, 0, 0, 0, 0, 0.0};
     const bool in = lane < Ns_;
     coop_stage<NMAX>(Ws, Wl, lane);
     if (flags & 1) {
@@ -276,6 +279,7 @@ __device__ __noinline__ VisitOut coop_visit_w(double* TB, double* Ws, lds_double
         }
         vo.sqp = 1;
         if (r.status == 1) vo.ipmcap = 1;
+        vo.gd = wave_sum(in ? gi * d : 0.0);
         if (in) {
             TB[(V_D * NMAX + lane) * 64 + s] = d;
             TB[(V_NL * NMAX + lane) * 64 + s] = nl;
@@ -305,6 +309,72 @@ __device__ __noinline__ double coop_visit_shift(double* TB, double* Ws, lds_doub
         coop_shift<NMAX>(Wl, Ws, Ns_, lane);
     }
     return fl;
+}
+
+// One backward pass over a lane's sample (lane-offset tiles, element k at
+// [k * 64]): the discrete adjoint of the RK4 shooting over the interval
+// derivatives ocp_shoot recorded, lambda_k = A_k (lambda_{k+1} + c_k) and
+// g_k = dphi/du_k = B_k (lambda_{k+1} + c_k) backwards from lambda_N = 0,
+// fused with, when kUpdate, the step of the
+// accepted line search (u += alpha d, s = alpha d, pi += alpha (nu - pi),
+// v = alpha v, y = g_new - g_old) and with the sums of the next KKT test,
+// so that an SQP iteration reads each tile once.  The tiles of 4 intervals
+// are loaded together ahead of their use.
+template <bool kUpdate>
+__device__ __forceinline__ KktSums adjoint_pass(int N, double alpha, const double* rec, double* U,
+                                                const double* Dv, double* PIL, double* PIU,
+                                                const double* NLv, const double* NUv, double* Sv,
+                                                double* Vv, double* G, double* Y) {
+    constexpr int kB = 4;
+    double lam = 0.0;
+    KktSums r{0.0, 0.0, false};
+#pragma unroll 1
+    for (int top = N - 1; top >= 0; top -= kB) {
+        double A[kB], Bv[kB], Cc[kB], G0[kB], u[kB], dv[kB], pl[kB], pu[kB], nl[kB], nu[kB],
+            vv[kB];
+#pragma unroll
+        for (int j = 0; j < kB; ++j) {
+            const int k = top - j >= 0 ? top - j : 0;
+            const double* const rr = rec + (int64_t)(3 * k) * kTile;
+            A[j] = rr[0];
+            Bv[j] = rr[kTile];
+            Cc[j] = rr[2 * kTile];
+            if (kUpdate) {
+                G0[j] = G[k * 64];
+                u[j] = U[k * 64];
+                dv[j] = Dv[k * 64];
+                pl[j] = PIL[k * 64];
+                pu[j] = PIU[k * 64];
+                nl[j] = NLv[k * 64];
+                nu[j] = NUv[k * 64];
+                vv[j] = Vv[k * 64];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kB; ++j) {
+            const int k = top - j;
+            if (k >= 0) {
+                lam += Cc[j];
+                const double gk = Bv[j] * lam;
+                lam = A[j] * lam;
+                double p_l = 0.0, p_u = 0.0;
+                if (kUpdate) {
+                    const double un = u[j] + alpha * dv[j];
+                    Sv[k * 64] = un - u[j];
+                    U[k * 64] = un;
+                    p_l = pl[j] + alpha * (nl[j] - pl[j]);
+                    p_u = pu[j] + alpha * (nu[j] - pu[j]);
+                    PIL[k * 64] = p_l;
+                    PIU[k * 64] = p_u;
+                    Vv[k * 64] = alpha * vv[j];
+                    Y[k * 64] = gk - G0[j];
+                }
+                G[k * 64] = gk;
+                kkt_add(r, gk, p_l, p_u);
+            }
+        }
+    }
+    return r;
 }
 
 // One SQP solve (SQP section, single shooting) for every lane with `live`;
@@ -352,11 +422,15 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
             coop_identity<NMAX>(nullptr, Wslot + (int64_t)s * NMAX * NMAX, Ns_, lane);
         }
     }
+    KktSums ks{0.0, 0.0, false};   // sums of the next KKT test
+    double Dl = 0.0;               // g'd of the last QP step
     if (live) {
         f = ocp_shoot<GMODE == 1>(p, N, xhat, i, su.istep, su.sign, U, Dv, 0.0, false, Xs);
         cnt[C_LS]++;
-        if (GMODE == 1) ocp_grad_adjoint(N, Xs, G, nullptr);
-        else ocp_grad_fwd<NMAX>(p, N, xhat, i, su.istep, su.sign, U, G, nullptr, Dv);
+        if (GMODE == 1)
+            ks = adjoint_pass<false>(N, 0.0, Xs, U, Dv, PIL, PIU, NLv, NUv, Sv, Vv, G, Yv);
+        else
+            ks = ocp_grad_fwd<NMAX>(p, N, xhat, i, su.istep, su.sign, U, G, nullptr, Dv, PIL, PIU);
         cnt[C_GRAD]++;
     }
     bool active = live, pending = false, converged = false;
@@ -364,21 +438,11 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
     for (;;) {
         // scaled KKT test, eq. (convergence), on the lanes still iterating
         if (active) {
-            // one pass: s1 and the largest |grad L|_k (dividing by sd > 0
-            // afterwards selects the same maximum as dividing each term)
-            double s1 = 0.0, rmax = 0.0;
-            bool bad = false;
-            #pragma unroll 4
-            for (int k = 0; k < N; ++k) {
-                const double pl = PIL[k * 64], pu = PIU[k * 64];
-                s1 += fabs(pl) + fabs(pu);
-                const double r = fabs(G[k * 64] - pl + pu);
-                bad |= (r != r);
-                rmax = r > rmax ? r : rmax;
-            }
-            const double sd = (s1 / (2.0 * N) > smax ? s1 / (2.0 * N) : smax) / smax;
-            const double kkt = rmax / sd;
-            bad |= (kkt != kkt);
+            // from the sums the gradient pass left (dividing the largest
+            // |grad L|_k by sd > 0 selects the same maximum as dividing each)
+            const double sd = (ks.s1 / (2.0 * N) > smax ? ks.s1 / (2.0 * N) : smax) / smax;
+            const double kkt = ks.rmax / sd;
+            const bool bad = ks.bad || (kkt != kkt);
             if (!bad && kkt <= p.sqp_eps) { converged = true; active = false; }
             else if (l == p.sqp_max_iter) { active = false; }
         }
@@ -399,6 +463,7 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
                     : coop_visit_w<NMAX>(TB, Ws, (lds_double*)Wl, Ns_, s, flags, p.umin, p.umax,
                                          p.ipm_max_iter, p.qp_solver);
             if (lane == s) {
+                Dl = vo.gd;
                 qfl += vo.fl;
                 cnt[C_SKIP] += vo.skip;
                 cnt[C_RESET] += vo.reset;
@@ -411,10 +476,8 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
         pending = false;
         if (ma == 0) break;
         // backtracking line search, eq. (Armijo), one sample per lane
-        double D = 0.0, alpha = 1.0;
-        if (active)
-            #pragma unroll 4
-            for (int k = 0; k < N; ++k) D += G[k * 64] * Dv[k * 64];
+        const double D = active ? Dl : 0.0;
+        double alpha = 1.0;
         bool searching = active;
         int bt = 0;
         while (__ballot(searching)) {
@@ -431,18 +494,21 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
             }
         }
         if (active) {
-            #pragma unroll 4
-            for (int k = 0; k < N; ++k) {
-                const double uo = U[k * 64];
-                const double un = uo + alpha * Dv[k * 64];
-                Sv[k * 64] = un - uo;
-                U[k * 64] = un;
-                PIL[k * 64] = PIL[k * 64] + alpha * (NLv[k * 64] - PIL[k * 64]);
-                PIU[k * 64] = PIU[k * 64] + alpha * (NUv[k * 64] - PIU[k * 64]);
-                Vv[k * 64] = alpha * Vv[k * 64];
+            if (GMODE == 1) {
+                ks = adjoint_pass<true>(N, alpha, Xs, U, Dv, PIL, PIU, NLv, NUv, Sv, Vv, G, Yv);
+            } else {
+                #pragma unroll 4
+                for (int k = 0; k < N; ++k) {
+                    const double uo = U[k * 64];
+                    const double un = uo + alpha * Dv[k * 64];
+                    Sv[k * 64] = un - uo;
+                    U[k * 64] = un;
+                    PIL[k * 64] = PIL[k * 64] + alpha * (NLv[k * 64] - PIL[k * 64]);
+                    PIU[k * 64] = PIU[k * 64] + alpha * (NUv[k * 64] - PIU[k * 64]);
+                    Vv[k * 64] = alpha * Vv[k * 64];
+                }
+                ks = ocp_grad_fwd<NMAX>(p, N, xhat, i, su.istep, su.sign, U, G, Yv, Dv, PIL, PIU);
             }
-            if (GMODE == 1) ocp_grad_adjoint(N, Xs, G, Yv);
-            else ocp_grad_fwd<NMAX>(p, N, xhat, i, su.istep, su.sign, U, G, Yv, Dv);
             cnt[C_GRAD]++;
             pending = true;
             ++l;
@@ -463,11 +529,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
     const double h = p.Ts / (double)p.Ns;
     const double sqh = sqrt(h);
 
+    const int g_hi = wk.qhi ? *wk.qhi : wk.n_groups;
     for (;;) {
         int grp = 0;
         if (lane == 0) grp = atomicAdd(wk.queue, 1);
         grp = __shfl(grp, 0, 64);
-        if (grp >= wk.n_groups) break;
+        if (grp >= g_hi) break;
         const int64_t idx = (int64_t)grp * wk.spw + lane;
         const bool has = lane < wk.spw && idx < wk.n_pos;
         const int64_t pos = has ? wk.pos[idx] : 0;
@@ -560,11 +627,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
 
 // PI closed loop, eq. (PI), one sample per lane.  With ck != null the plant
 // state (n, I-hat) at the start of every interval i = 0, C, 2C, ... is kept
-// for the reverse pass: ck[((i / C) * 4 + f) * npi + t].
+// for the reverse pass: ck[((i / C) * 4 + f) * npi + t].  With ctl != null
+// the launch covers the PI samples [c ppc, (c + 1) ppc) of chunk c = *ctl.
 __global__ __launch_bounds__(64) void pi_kernel(DevParams p, const int64_t* pos_list, int64_t npi,
-                                                Outs out, double* ck) {
-    const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (t >= npi) return;
+                                                Outs out, double* ck, const int* ctl, int64_t ppc) {
+    int64_t t1 = npi, t = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (ctl) {
+        const int64_t t0 = (int64_t)(*ctl) * ppc;
+        t += t0;
+        t1 = t0 + ppc < npi ? t0 + ppc : npi;
+    }
+    if (t >= t1) return;
     const int64_t pos = pos_list[t];
     const Setup su = sample_setup(p, p.id_offset + pos);
     const double sqrtR = sqrt(p.Rmeas);

@@ -50,6 +50,7 @@ BASE = dict(
     ckpt_interval=0,               # PI reverse pass checkpoint spacing (0: library default)
     samples_per_wave=0,            # NMPC lanes per wavefront (0: library plan)
     qp_solver=2,                   # 2 inverse form, 1 active set on W, 0 interior point on W
+    chunk_samples=0,               # > 0: chunked run, one captured graph replay per chunk
 )
 
 

@@ -63,7 +63,8 @@ def _c_layout(struct, fields):
 
 @pytest.mark.parametrize("cstruct,pystruct", [("mc_cl_params", binding.Params),
                                               ("mc_cl_outputs", binding.Outputs),
-                                              ("mc_cl_stats", binding.Stats)])
+                                              ("mc_cl_stats", binding.Stats),
+                                              ("mc_cl_tune_result", binding.TuneResult)])
 def test_struct_layout_matches_header(cstruct, pystruct):
     fields = [f for f, _ in pystruct._fields_]
     size, offs = _c_layout(cstruct, fields)
@@ -87,7 +88,8 @@ def _create(cfg, **over):
 @pytest.mark.parametrize("over", [dict(V=0.0), dict(N=0), dict(N=65), dict(umin=5.0, umax=1.0),
                                   dict(n_samples=0), dict(Ns=0), dict(k0=float("nan")),
                                   dict(Ts=-1.0), dict(grad_mode=2), dict(P0=0.0),
-                                  dict(sp_z=(250.0,), sp_i=(0,)), dict(kP=0.0)])
+                                  dict(sp_z=(250.0,), sp_i=(0,)), dict(kP=0.0),
+                                  dict(chunk_samples=-1)])
 def test_invalid_parameters_are_rejected_before_any_device_call(lib, over):
     from paper_2212_02197_amd import workloads
     assert _create(workloads.c0_small_nmpc(), **over) == -1
@@ -110,3 +112,8 @@ def test_calls_on_null_context_fail_cleanly(lib):
     g = (C.c_double * 2)()
     assert lib.mc_cl_grad(None, None, g, None) == -1
     assert lib.mc_cl_run(None, None, None) == -1
+
+
+def test_tune_rejects_bad_arguments(lib):
+    r = binding.TuneResult()
+    assert lib.mc_cl_tune(None, None, 6, C.byref(r)) == -1

@@ -266,3 +266,86 @@ def test_mixed_horizons_share_wave_slots():
     # transient from inlet conditions leaves about a fifth of them so
     good = compare_conditioned(cfg, phi, ps, ref, "mixed N")
     assert good.sum() >= len(good) // 2
+
+
+def test_pi_autograd_function():
+    # d mean Phi / d(Kc, tau_i) through torch.autograd over the library's
+    # checkpointed reverse pass, against the mean of the oracle's pathwise
+    # tangents d Phi_s / d(Kc, tau_i) and a central difference of the GPU
+    # forward pass (relative step 1e-6)
+    cfg = W.c2_pi_adjoint(n_samples=64, L=300, ckpt_interval=25)
+    Kc, taui = cfg["kP"], cfg["kP"] / cfg["kI"]
+    theta = torch.tensor([Kc, taui], dtype=torch.float64, device="cuda", requires_grad=True)
+    phi = binding.pi_closed_loop(theta, cfg)
+    loss = phi.mean()
+    loss.backward()
+    g = theta.grad.cpu().numpy()
+    ref = oracle_run(cfg)
+    g_ref = ref["dphi"].mean(axis=0)
+    np.testing.assert_allclose(g, g_ref, rtol=1e-9)
+    assert float(loss) == pytest.approx(ref["phi"].mean(), rel=1e-9)
+    for b in range(2):
+        h = 1e-6 * abs(float(theta[b]))
+        vals = []
+        for sgn in (1, -1):
+            th = theta.detach().clone()
+            th[b] += sgn * h
+            vals.append(float(binding.pi_closed_loop(th, cfg).mean()))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        print("autograd", b, g[b], "central difference", fd, flush=True)
+        assert g[b] == pytest.approx(fd, rel=1e-4, abs=1e-6 * abs(g).max())
+
+
+def test_chunked_graph_run_matches_single_launch():
+    # c4's mix (NMPC N = 25 below the split, PI above, +-10 % setpoint step)
+    # in 5 chunks, each one replay of the captured chunk step: bitwise the
+    # single-launch results, on every replay, and the oracle's on a sample
+    cfg = W.c4_mixed(n_samples=600, kind_split=300, noise_mod=300, L=12, sp_step_lo=3,
+                     sp_step_hi=9)
+    phi1, st1, ps1, _ = gpu_run(cfg)
+    camp = binding.Campaign(dict(cfg, chunk_samples=130))
+    outs = []
+    for rep in range(3):
+        camp.run()
+        phi, st = camp.costs()
+        ps = camp.per_sample()
+        outs.append((phi, ps))
+        torch.cuda.synchronize()
+    camp.close()
+    for phi, ps in outs:
+        np.testing.assert_array_equal(phi, phi1)
+        np.testing.assert_array_equal(ps["ashash"], ps1["ashash"])
+        for f in binding.CNT_NAMES:
+            np.testing.assert_array_equal(ps[f], ps1[f], err_msg=f)
+    ids = np.arange(0, 600, 37)
+    ref = oracle_run(cfg, ids=ids)
+    compare(phi1, ps1, ref, sel=ids, tag="c4 chunked")
+
+
+def test_tune_keeps_results_and_picks_a_candidate():
+    cfg = W.c0_small_nmpc(n_samples=300, L=10, kind_split=200, noise_mod=200)
+    phi0, _, ps0, _ = gpu_run(cfg)
+    camp = binding.Campaign(dict(cfg, want_grad=1))
+    res = camp.tune(trial_intervals=3)
+    print("tune", res, flush=True)
+    assert res["classes"][0]["spw"] in binding.TUNE_SPW
+    assert all(v > 0 for v in res["classes"][0]["trial_ms"].values())
+    assert res["ckpt_interval"] in binding.TUNE_CKPT
+    assert camp.plan()[0]["spw"] == res["classes"][0]["spw"]
+    camp.run()
+    phi, st = camp.costs()
+    ps = camp.per_sample()
+    g, _ = camp.grad()
+    camp.close()
+    np.testing.assert_array_equal(phi, phi0)
+    np.testing.assert_array_equal(ps["ashash"], ps0["ashash"])
+    # the checkpoint interval moves the gradient by rounding only (each
+    # segment is recomputed from its checkpoint by the reverse kernel's own
+    # code, whose rounding may differ from the forward kernel's)
+    camp = binding.Campaign(dict(cfg, want_grad=1, ckpt_interval=3))
+    camp.run()
+    camp.costs()
+    g3, _ = camp.grad()
+    camp.close()
+    assert g[0] == pytest.approx(g3[0], rel=1e-12)
+    assert g[1] == pytest.approx(g3[1], rel=1e-12)
