@@ -76,7 +76,10 @@ __device__ __forceinline__ double wave_min(double v) {
 
 // Stage the sample's W (NMAX x NMAX doubles, 16-byte aligned) into LDS with
 // direct global-to-LDS loads: 1 KB per instruction, no registers involved,
-// all in flight together.  coop_stage_issue waits for this wave's earlier
+// all in flight together.  The matrices (32 KB per sample, a wavefront's
+// next visit reads another sample's) are loaded and written back
+// non-temporal, so that their stream does not evict the lane tiles, which a
+// wavefront reads again in every SQP iteration, from the caches.  coop_stage_issue waits for this wave's earlier
 // stores (to W among them) and issues the loads; coop_stage_wait waits for
 // every load in flight (other loads issued in between complete with them).
 template <int NMAX>
@@ -87,7 +90,7 @@ __device__ __forceinline__ void coop_stage_issue(const double* __restrict__ Wg, 
     for (int q = 0; q < NMAX * NMAX / 128; ++q)
         __builtin_amdgcn_global_load_lds(
             (const void __attribute__((address_space(1)))*)(Wg + q * 128 + 2 * lane),
-            (void __attribute__((address_space(3)))*)(Wl + q * 128), 16, 0, 0);
+            (void __attribute__((address_space(3)))*)(Wl + q * 128), 16, 0, 2 /* nt */);
 }
 __device__ __forceinline__ void coop_stage_wait() {
     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
@@ -423,7 +426,7 @@ __device__ __forceinline__ int coop_bfgs(double* Wl, double* __restrict__ Wg, in
                 const double t2 = readlane_d(ra, j) * r;
                 const double w = (col[j] - t1 / sWs) + t2 / sr;
                 Wl[j * NMAX + lane] = w;
-                Wg[j * NMAX + lane] = w;
+                __builtin_nontemporal_store(w, &Wg[j * NMAX + lane]);
             }
         }
     }
@@ -441,7 +444,7 @@ __device__ __forceinline__ void coop_identity(double* Wl, double* __restrict__ W
 #pragma unroll
         for (int j = 0; j < NMAX; ++j) {
             const double v = (j == lane) ? 1.0 : 0.0;
-            Wg[j * NMAX + lane] = v;
+            __builtin_nontemporal_store(v, &Wg[j * NMAX + lane]);
             if (Wl) Wl[j * NMAX + lane] = v;
         }
     }
@@ -462,7 +465,7 @@ __device__ __forceinline__ void coop_shift(const double* Wl, double* __restrict_
                 double w = 0.0;
                 if (lane < N - 1 && j < N - 1) w = Wl[(j + 1) * NMAX + (lane + 1)];
                 if (lane == N - 1 && j == N - 1) w = last;
-                Wg[j * NMAX + lane] = w;
+                __builtin_nontemporal_store(w, &Wg[j * NMAX + lane]);
             }
         }
     }
@@ -570,7 +573,7 @@ __device__ __forceinline__ int coop_bfgs_h(double* Hl, double* __restrict__ Hg, 
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 Hl[(j + q) * NMAX + lane] = t[q];
-                Hg[(j + q) * NMAX + lane] = t[q];
+                __builtin_nontemporal_store(t[q], &Hg[(j + q) * NMAX + lane]);
             }
         }
     }
@@ -772,7 +775,7 @@ __device__ __forceinline__ void coop_shift_h(const double* Hl, double* __restric
             const double p = readlane_d(fi, j) * fi;
             double w = Hl[jr * NMAX + li] - p * inv_e;
             if (!(lane < N - 1 && j < N - 1)) w = (lane == N - 1 && j == N - 1) ? hlast : 0.0;
-            Hg[j * NMAX + lane] = w;
+            __builtin_nontemporal_store(w, &Hg[j * NMAX + lane]);
         }
     }
     __syncthreads();
