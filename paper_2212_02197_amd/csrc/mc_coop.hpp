@@ -495,34 +495,48 @@ __device__ __forceinline__ int rows8(int N) {
     return r < NMAX ? r : NMAX;
 }
 
+// The staging buffer is followed by two vectors of NMAX doubles, through
+// which a value of every lane is broadcast to all lanes: each lane writes
+// its element, and a read of one address by every lane returns it to all
+// (an LDS broadcast, one instruction for two doubles, against four
+// v_readlane per two doubles).
+template <int NMAX>
+__device__ __forceinline__ double* lds_vec(double* Hl, int k) {
+    return Hl + NMAX * NMAX + k * NMAX;
+}
+template <int NMAX>
+__device__ __forceinline__ const double* lds_vec(const double* Hl, int k) {
+    return Hl + NMAX * NMAX + k * NMAX;
+}
+
 // (H x)_i on lane i < N from the staged H (lane i reads its column, H
-// symmetric); x_j is broadcast from lane j and must be 0 on lanes >= N;
-// the result is 0 on lanes >= N.  Eight rows per step with their LDS
-// reads issued one step ahead; four partial sums.
+// symmetric); x_j, broadcast from lane j through the first LDS vector, must
+// be 0 on lanes >= N; the result is 0 on lanes >= N.  Eight rows per step,
+// four partial sums.
 template <int NMAX>
 __device__ __forceinline__ double coop_matvec(const double* Hl, int N, int lane, double x) {
     const int lc = lane < NMAX ? lane : NMAX - 1;
     const int R = rows8<NMAX>(N);
+    double* const xl = lds_vec<NMAX>((double*)Hl, 0);
+    __syncthreads();   // earlier readers of the vector are done
+    if (lane < NMAX) xl[lane] = x;
+    __syncthreads();
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    double h[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) h[q] = Hl[q * NMAX + lc];
-    #pragma unroll 1
+    #pragma unroll 2
     for (int j = 0; j < R; j += 8) {
-        double hn[8];
-        const int jn = j + 8 < R ? j + 8 : j;
+        double h[8], xv[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) hn[q] = Hl[(jn + q) * NMAX + lc];
-        a0 = fma(h[0], readlane_d(x, j + 0), a0);
-        a1 = fma(h[1], readlane_d(x, j + 1), a1);
-        a2 = fma(h[2], readlane_d(x, j + 2), a2);
-        a3 = fma(h[3], readlane_d(x, j + 3), a3);
-        a0 = fma(h[4], readlane_d(x, j + 4), a0);
-        a1 = fma(h[5], readlane_d(x, j + 5), a1);
-        a2 = fma(h[6], readlane_d(x, j + 6), a2);
-        a3 = fma(h[7], readlane_d(x, j + 7), a3);
+        for (int q = 0; q < 8; ++q) h[q] = Hl[(j + q) * NMAX + lc];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) h[q] = hn[q];
+        for (int q = 0; q < 8; ++q) xv[q] = xl[j + q];
+        a0 = fma(h[0], xv[0], a0);
+        a1 = fma(h[1], xv[1], a1);
+        a2 = fma(h[2], xv[2], a2);
+        a3 = fma(h[3], xv[3], a3);
+        a0 = fma(h[4], xv[4], a0);
+        a1 = fma(h[5], xv[5], a1);
+        a2 = fma(h[6], xv[6], a2);
+        a3 = fma(h[7], xv[7], a3);
     }
     const double acc = (a0 + a1) + (a2 + a3);
     return lane < N ? acc : 0.0;
@@ -558,7 +572,14 @@ __device__ __forceinline__ int coop_bfgs_h(double* Hl, double* __restrict__ Hg, 
     const double c = rho * rho * rHr + rho;
     const double a1 = c * s - rho * Hr;   // multiplies s_j
     const double a2 = -rho * s;           // multiplies (Hr)_j
-    __syncthreads();   // every lane has read H for Hr
+    __syncthreads();   // every lane has read H and the broadcast vector for Hr
+    double* const sl = lds_vec<NMAX>(Hl, 0);
+    double* const hrl = lds_vec<NMAX>(Hl, 1);
+    if (lane < NMAX) {
+        sl[lane] = s;
+        hrl[lane] = Hr;
+    }
+    __syncthreads();
     if (act) {
         // rows N..R-1 see s_j = (Hr)_j = 0 and are written back unchanged
         const int R = rows8<NMAX>(N);
@@ -569,7 +590,7 @@ __device__ __forceinline__ int coop_bfgs_h(double* Hl, double* __restrict__ Hg, 
             for (int q = 0; q < 8; ++q) t[q] = Hl[(j + q) * NMAX + lane];
 #pragma unroll
             for (int q = 0; q < 8; ++q)
-                t[q] = fma(a2, readlane_d(Hr, j + q), fma(a1, readlane_d(s, j + q), t[q]));
+                t[q] = fma(a2, hrl[j + q], fma(a1, sl[j + q], t[q]));
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 Hl[(j + q) * NMAX + lane] = t[q];
@@ -709,12 +730,18 @@ __device__ __forceinline__ QPResult coop_box_qp_h(const double* Hl, lds_double* 
                 res.iters = it + 1;
                 return res;
             }
+            // d_I = -(H g)_I + H_IA lam_A, lam_A broadcast from the
+            // compressed solution through the first LDS vector
+            double* const xl = lds_vec<NMAX>((double*)Hl, 0);
+            __syncthreads();
+            if (lane < NMAX) xl[lane] = xc;
+            __syncthreads();
             uint64_t mm = amask;
             #pragma unroll 1
             for (int k = 0; k < m; ++k) {
                 const int a = __ffsll((unsigned long long)mm) - 1;
                 mm &= mm - 1;
-                acc = fma(Hl[a * NMAX + lc], readlane_d(xc, k), acc);
+                acc = fma(Hl[a * NMAX + lc], xl[k], acc);
             }
             const double mf = m;
             fl += mf * mf * mf / 3.0 + 2.0 * mf * mf + 2.0 * n * mf;

@@ -519,7 +519,8 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
 
 template <int NMAX, int GMODE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVES_PER_EU))) void nmpc_kernel(DevParams p, NmpcWork wk, Outs out) {
-    __shared__ __attribute__((aligned(16))) double Wl[NMAX * NMAX];   // staged W (or H) of one sample
+    // staged W (or H) of one sample, then two broadcast vectors (lds_vec)
+    __shared__ __attribute__((aligned(16))) double Wl[NMAX * NMAX + 2 * NMAX];
     const int lane = threadIdx.x;
     double* const TB = wk.tiles + (int64_t)blockIdx.x * wk.tile_stride;
     double* const XS = wk.xs + (int64_t)blockIdx.x * wk.xs_stride;
