@@ -383,7 +383,7 @@ __device__ __forceinline__ KktSums adjoint_pass(int N, double alpha, const doubl
 template <int NMAX, int GMODE>
 __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, int i, const Setup& su,
                           double xhat, int lane, double* TB, double* XS, double* Wslot,
-                          double* Wl, int (&cnt)[C_NCNT], double& qfl) {
+                          double* Wl, int (&cnt)[C_NCNT], double& qfl, bool pair_ls) {
     double* const U = TB + (V_U * NMAX) * 64 + lane;
     double* const G = TB + (V_G * NMAX) * 64 + lane;
     double* const Dv = TB + (V_D * NMAX) * 64 + lane;
@@ -480,22 +480,79 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
         double alpha = 1.0;
         bool searching = active;
         int bt = 0;
-        while (__ballot(searching)) {
-            if (searching) {
-                const double ft =
-                    ocp_shoot<GMODE == 1>(p, N, xhat, i, su.istep, su.sign, U, Dv, alpha, true, Xs);
-                cnt[C_LS]++;
-                bool accept = false;
-                if (bt == 0 && -D <= 64.0 * DBL_EPSILON * (1.0 + fabs(f))) accept = true;
-                else if (ft <= f + p.ls_c1 * alpha * D) accept = true;
-                else if (bt == p.ls_max_bt) { cnt[C_LSCAP]++; accept = true; }
-                if (accept) { searching = false; f = ft; }
-                else { alpha = p.ls_beta * alpha; ++bt; }
+        int rec_off = 0;   // column offset of the accepted trial's shooting record
+        if (pair_ls) {
+            // At most 32 samples per wavefront: lane l + 32, idle in the lane
+            // phases, evaluates the trial after lane l's (step beta alpha,
+            // its record in its own column) in the same pass, so a wavefront
+            // whose lanes backtrack once pays one shooting pass, not two.
+            // Lane l takes the first acceptable of the two in order, which
+            // is the step, objective and counts of the serial search.
+            const int src = lane & 31;
+            const bool partner = lane >= 32;
+            const int Np = __shfl(N, src, 64);
+            const double xp = __shfl(xhat, src, 64);
+            const int isp = __shfl(su.istep, src, 64);
+            const double sgp = __shfl(su.sign, src, 64);
+            double* const Up = TB + (V_U * NMAX) * 64 + src;
+            double* const Dp = TB + (V_D * NMAX) * 64 + src;
+            for (;;) {
+                const bool s_on = __shfl(searching ? 1 : 0, src, 64) != 0;
+                if (!__ballot(s_on)) break;
+                const int bt_o = __shfl(bt, src, 64);
+                const double a_o = __shfl(alpha, src, 64);
+                const int my_bt = partner ? bt_o + 1 : bt_o;
+                const double my_a = partner ? p.ls_beta * a_o : a_o;
+                double ft = 0.0;
+                if (s_on && my_bt <= p.ls_max_bt)
+                    ft = ocp_shoot<GMODE == 1>(p, Np, xp, i, isp, sgp, Up, Dp, my_a, true, Xs);
+                const double ft2 = __shfl(ft, (lane + 32) & 63, 64);
+                if (!partner && searching) {
+                    cnt[C_LS]++;
+                    bool accept = false;
+                    if (bt == 0 && -D <= 64.0 * DBL_EPSILON * (1.0 + fabs(f))) accept = true;
+                    else if (ft <= f + p.ls_c1 * alpha * D) accept = true;
+                    else if (bt == p.ls_max_bt) { cnt[C_LSCAP]++; accept = true; }
+                    if (accept) {
+                        searching = false;
+                        f = ft;
+                        rec_off = 0;
+                    } else {
+                        // the partner's trial: bt + 1 <= ls_max_bt here
+                        alpha = p.ls_beta * alpha;
+                        ++bt;
+                        cnt[C_LS]++;
+                        if (ft2 <= f + p.ls_c1 * alpha * D) accept = true;
+                        else if (bt == p.ls_max_bt) { cnt[C_LSCAP]++; accept = true; }
+                        if (accept) {
+                            searching = false;
+                            f = ft2;
+                            rec_off = 32;
+                        } else {
+                            alpha = p.ls_beta * alpha;
+                            ++bt;
+                        }
+                    }
+                }
+            }
+        } else {
+            while (__ballot(searching)) {
+                if (searching) {
+                    const double ft =
+                        ocp_shoot<GMODE == 1>(p, N, xhat, i, su.istep, su.sign, U, Dv, alpha, true, Xs);
+                    cnt[C_LS]++;
+                    bool accept = false;
+                    if (bt == 0 && -D <= 64.0 * DBL_EPSILON * (1.0 + fabs(f))) accept = true;
+                    else if (ft <= f + p.ls_c1 * alpha * D) accept = true;
+                    else if (bt == p.ls_max_bt) { cnt[C_LSCAP]++; accept = true; }
+                    if (accept) { searching = false; f = ft; }
+                    else { alpha = p.ls_beta * alpha; ++bt; }
+                }
             }
         }
         if (active) {
             if (GMODE == 1) {
-                ks = adjoint_pass<true>(N, alpha, Xs, U, Dv, PIL, PIU, NLv, NUv, Sv, Vv, G, Yv);
+                ks = adjoint_pass<true>(N, alpha, Xs + rec_off, U, Dv, PIL, PIU, NLv, NUv, Sv, Vv, G, Yv);
             } else {
                 #pragma unroll 4
                 for (int k = 0; k < N; ++k) {
@@ -572,7 +629,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
                 if (!isfinite(xhat) || !isfinite(P)) cnt[C_NONFIN] = 1;
             }
             const bool conv = sqp_group<NMAX, GMODE>(p, step, N, i, su, xhat, lane, TB, XS, Wslot,
-                                                     Wl, cnt, qfl);
+                                                     Wl, cnt, qfl, wk.spw <= 32);
             if (p.hess_warm) {
                 uint64_t m = __ballot(step);
                 while (m) {
