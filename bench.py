@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the planned launch shape (skip the measured tuning)")
     ap.add_argument("--tune-intervals", type=int, default=6)
+    ap.add_argument("--cu-scaling", action="store_true",
+                    help="also measure NMPC throughput against compute units (CU-masked streams)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain elementwise copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -170,6 +172,7 @@ def main():
         log("adjoint vs plain done")
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, args.cpu_seconds)
+    scaling = cu_scaling(cfg) if args.cu_scaling else None
 
     out = {
         "metric": "NMPC CSTR closed-loop sims/sec on 1 GPU; % FP64 peak; adjoint vs plain SQP",
@@ -195,10 +198,43 @@ def main():
                 "mean_pi": stats["mean"][1], "var_pi": stats["var"][1]},
         "launch_plan": plan,
         "launch_tuning": tuning,
+        "cu_scaling": scaling,
         "adjoint_vs_plain": plain,
         "algorithmic_gflop_per_step": round(camp_flops / 1e9, 3),
     }
     print(json.dumps(out))
+
+
+def cu_scaling(cfg, samples=32768, L=20, spw=32):
+    """Fixed work (the first L intervals of `samples` NMPC closed loops of the
+    workload, 32 per wavefront) on streams limited to the first k compute
+    units: the GPU analogue of the paper's speed-up against CPU cores."""
+    import torch
+
+    from paper_2212_02197_amd import binding
+    total = torch.cuda.get_device_properties(0).multi_processor_count
+    ks = [k for k in (8, 16, 32, 64, 128, 256) if k <= total]
+    rows = []
+    for k in ks:
+        cs = binding.CuStream(k)
+        c = dict(cfg, n_samples=samples, kind_split=-1, default_kind=0, noise_mod=0, L=L,
+                 cu_limit=k, samples_per_wave=spw)
+        camp = binding.Campaign(c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        camp.run(stream=cs.stream)
+        camp.costs()
+        dt = time.perf_counter() - t0
+        rows.append(dict(cus=k, sims_per_s=round(samples / dt, 3), ms=round(dt * 1000.0, 1),
+                         waves=camp.plan()[0]["slots"]))
+        camp.close()
+        cs.close()
+        log(f"cu scaling: {k} CUs, {samples} samples x {L} intervals in {dt:.2f} s")
+    k0, r0 = rows[0]["cus"], rows[0]["sims_per_s"]
+    for r in rows:
+        r["speedup"] = round(r["sims_per_s"] / r0, 3)
+        r["efficiency"] = round(r["speedup"] / (r["cus"] / k0), 3)
+    return dict(samples=samples, intervals=L, samples_per_wave=spw, rows=rows)
 
 
 def adjoint_vs_plain(cfg, n):

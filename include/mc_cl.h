@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define MC_CL_ABI_VERSION 2u
+#define MC_CL_ABI_VERSION 3u
 #define MC_CL_SPMAX 8        /* setpoint schedule levels                        */
 #define MC_CL_NMAX 64        /* largest NMPC horizon                            */
 #define MC_CL_NHIST 202      /* histogram: underflow, 200 bins, overflow        */
@@ -139,6 +139,11 @@ typedef struct {
      * bitwise the same either way.  Trajectory outputs need chunk_samples =
      * 0 (EUNSUPPORTED otherwise).                                           */
     int32_t chunk_samples;
+    /* > 0: plan the launches for this many compute units (at most the
+     * device's), for runs on a stream limited to them (mc_cl_stream_create);
+     * 0: all of the device's compute units.                                 */
+    int32_t cu_limit;
+    int32_t reserved0;
 } mc_cl_params;
 
 /* Optional outputs of mc_cl_run; every pointer may be NULL.  All are device
@@ -239,6 +244,15 @@ typedef struct {
     float grad_ms[MC_CL_TUNE_NCK];        /* trial time per candidate C      */
 } mc_cl_tune_result;
 int mc_cl_tune(mc_cl_ctx *c, void *hip_stream, int32_t trial_intervals, mc_cl_tune_result *r);
+
+/* A HIP stream on the current device whose kernels run on its first n_cu
+ * compute units only (a CU-masked stream; n_cu <= 0 or >= the device's
+ * count: all), for throughput against compute units (the GPU analogue of
+ * the Parallel scalability study).  Pair it with mc_cl_params.cu_limit =
+ * n_cu.  *stream receives the hipStream_t, owned by the caller and released
+ * with mc_cl_stream_destroy.  EINVAL for a null argument; EHIP.            */
+int mc_cl_stream_create(int32_t n_cu, void **stream);
+int mc_cl_stream_destroy(void *stream);
 
 #ifdef __cplusplus
 }

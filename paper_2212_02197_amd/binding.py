@@ -20,7 +20,7 @@ CNT_NAMES = ["kind", "N", "L", "n_ocp", "n_ocp_fail", "sqp_iter", "ipm_iter", "l
 NCNT = len(CNT_NAMES)
 STATUS = {0: "MC_CL_OK", -1: "MC_CL_EINVAL", -2: "MC_CL_EHIP", -3: "MC_CL_ENOMEM",
           -4: "MC_CL_ESTATE", -5: "MC_CL_EUNSUPPORTED"}
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 
 class Params(C.Structure):
@@ -52,6 +52,7 @@ class Params(C.Structure):
         ("noise_scale", C.c_double),
         ("ckpt_interval", C.c_int32), ("samples_per_wave", C.c_int32),
         ("qp_solver", C.c_int32), ("chunk_samples", C.c_int32),
+        ("cu_limit", C.c_int32), ("reserved0", C.c_int32),
     ]
 
 
@@ -79,7 +80,7 @@ class TuneResult(C.Structure):
 
 EXPORTS = ["mc_cl_create", "mc_cl_run", "mc_cl_costs", "mc_cl_grad", "mc_cl_destroy",
            "mc_cl_strerror", "mc_cl_abi_version", "mc_cl_kernel_ms", "mc_cl_plan",
-           "mc_cl_tune"]
+           "mc_cl_tune", "mc_cl_stream_create", "mc_cl_stream_destroy"]
 
 _lib = None
 
@@ -116,6 +117,10 @@ def lib():
         L.mc_cl_plan.argtypes = [vp, C.POINTER(C.c_int32), C.c_int]
         L.mc_cl_tune.restype = C.c_int
         L.mc_cl_tune.argtypes = [vp, vp, C.c_int32, C.POINTER(TuneResult)]
+        L.mc_cl_stream_create.restype = C.c_int
+        L.mc_cl_stream_create.argtypes = [C.c_int32, C.POINTER(vp)]
+        L.mc_cl_stream_destroy.restype = C.c_int
+        L.mc_cl_stream_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -144,6 +149,7 @@ def params(cfg: dict) -> Params:
     p.samples_per_wave = cfg.get("samples_per_wave", 0)
     p.qp_solver = cfg.get("qp_solver", 2)
     p.chunk_samples = cfg.get("chunk_samples", 0)
+    p.cu_limit = cfg.get("cu_limit", 0)
     for a in range(3):
         p.sigma[a] = cfg["sigma"][a]
     sp_i, sp_z = cfg["sp_i"], cfg["sp_z"]
@@ -315,3 +321,20 @@ def pi_closed_loop(theta, cfg):
     if _PI_FN is None:
         _PI_FN = _pi_closed_loop_function()
     return _PI_FN.apply(theta, cfg)
+
+
+class CuStream:
+    """A stream limited to the first n_cu compute units (mc_cl_stream_create),
+    as a torch external stream; close() releases it."""
+
+    def __init__(self, n_cu: int):
+        import torch
+        h = C.c_void_p()
+        _check(lib().mc_cl_stream_create(int(n_cu), C.byref(h)), "mc_cl_stream_create")
+        self.h = h
+        self.stream = torch.cuda.ExternalStream(h.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mc_cl_stream_destroy(self.h)
+            self.h = None

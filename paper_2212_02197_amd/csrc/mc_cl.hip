@@ -247,7 +247,7 @@ static int validate(const mc_cl_params* p) {
     if (p->ckpt_interval < 0 || p->samples_per_wave < 0 || p->samples_per_wave > 64)
         return MC_CL_EINVAL;
     if (p->qp_solver < 0 || p->qp_solver > 2) return MC_CL_EINVAL;
-    if (p->chunk_samples < 0) return MC_CL_EINVAL;
+    if (p->chunk_samples < 0 || p->cu_limit < 0) return MC_CL_EINVAL;
     if (p->sample_id_offset < 0 || p->sample_id_offset + p->n_samples > (int64_t)UINT32_MAX)
         return MC_CL_EINVAL;
     return MC_CL_OK;
@@ -462,6 +462,7 @@ int mc_cl_create(const mc_cl_params* p, mc_cl_ctx** out) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return fail(MC_CL_EHIP);
     c->n_cu = prop.multiProcessorCount;
+    if (p->cu_limit > 0 && p->cu_limit < c->n_cu) c->n_cu = p->cu_limit;
     const int64_t S = c->S;
 
     // plan: per-sample kind / N / L on the device
@@ -760,6 +761,29 @@ int mc_cl_tune(mc_cl_ctx* c, void* hip_stream, int32_t trial_intervals, mc_cl_tu
     c->ran = false;
     c->grad_ran = false;
     return rc;
+}
+
+int mc_cl_stream_create(int32_t n_cu, void** stream) {
+    if (!stream) return MC_CL_EINVAL;
+    *stream = nullptr;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    const int total = prop.multiProcessorCount;
+    const int n = (n_cu <= 0 || n_cu > total) ? total : n_cu;
+    std::vector<uint32_t> mask((size_t)(total + 31) / 32, 0u);
+    for (int k = 0; k < n; ++k) mask[(size_t)k / 32] |= 1u << (k % 32);
+    hipStream_t st = nullptr;
+    HIPCHK(hipExtStreamCreateWithCUMask(&st, (uint32_t)mask.size(), mask.data()));
+    *stream = (void*)st;
+    return MC_CL_OK;
+}
+
+int mc_cl_stream_destroy(void* stream) {
+    if (!stream) return MC_CL_EINVAL;
+    HIPCHK(hipStreamDestroy((hipStream_t)stream));
+    return MC_CL_OK;
 }
 
 int mc_cl_plan(mc_cl_ctx* c, int32_t* out, int max_classes) {

@@ -51,6 +51,7 @@ BASE = dict(
     samples_per_wave=0,            # NMPC lanes per wavefront (0: library plan)
     qp_solver=2,                   # 2 inverse form, 1 active set on W, 0 interior point on W
     chunk_samples=0,               # > 0: chunked run, one captured graph replay per chunk
+    cu_limit=0,                    # > 0: plan for this many compute units (CU-masked stream)
 )
 
 

@@ -89,7 +89,7 @@ def _create(cfg, **over):
                                   dict(n_samples=0), dict(Ns=0), dict(k0=float("nan")),
                                   dict(Ts=-1.0), dict(grad_mode=2), dict(P0=0.0),
                                   dict(sp_z=(250.0,), sp_i=(0,)), dict(kP=0.0),
-                                  dict(chunk_samples=-1)])
+                                  dict(chunk_samples=-1), dict(cu_limit=-1)])
 def test_invalid_parameters_are_rejected_before_any_device_call(lib, over):
     from paper_2212_02197_amd import workloads
     assert _create(workloads.c0_small_nmpc(), **over) == -1
@@ -117,3 +117,8 @@ def test_calls_on_null_context_fail_cleanly(lib):
 def test_tune_rejects_bad_arguments(lib):
     r = binding.TuneResult()
     assert lib.mc_cl_tune(None, None, 6, C.byref(r)) == -1
+
+
+def test_stream_helpers_reject_null(lib):
+    assert lib.mc_cl_stream_create(4, None) == -1
+    assert lib.mc_cl_stream_destroy(None) == -1

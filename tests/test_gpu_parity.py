@@ -349,3 +349,21 @@ def test_tune_keeps_results_and_picks_a_candidate():
     camp.close()
     assert g[0] == pytest.approx(g3[0], rel=1e-12)
     assert g[1] == pytest.approx(g3[1], rel=1e-12)
+
+
+def test_cu_limited_stream_matches_full_device():
+    # planning for 16 compute units and running on a stream limited to them
+    # changes the launch shape only: results bitwise equal, and the oracle's
+    cfg = W.c0_small_nmpc(n_samples=70, L=6)
+    phi0, _, ps0, _ = gpu_run(cfg)
+    cs = binding.CuStream(16)
+    camp = binding.Campaign(dict(cfg, cu_limit=16))
+    camp.run(stream=cs.stream)
+    phi, _ = camp.costs()
+    ps = camp.per_sample()
+    camp.close()
+    cs.close()
+    np.testing.assert_array_equal(phi, phi0)
+    np.testing.assert_array_equal(ps["ashash"], ps0["ashash"])
+    ref = oracle_run(cfg)
+    compare(phi, ps, ref, tag="cu16")
