@@ -318,14 +318,14 @@ __device__ __noinline__ double coop_visit_shift(double* TB, double* Ws, lds_doub
 // fused with, when kUpdate, the step of the
 // accepted line search (u += alpha d, s = alpha d, pi += alpha (nu - pi),
 // v = alpha v, y = g_new - g_old) and with the sums of the next KKT test,
-// so that an SQP iteration reads each tile once.  The tiles of 4 intervals
+// so that an SQP iteration reads each tile once.  The tiles of 8 intervals
 // are loaded together ahead of their use.
 template <bool kUpdate>
 __device__ __forceinline__ KktSums adjoint_pass(int N, double alpha, const double* rec, double* U,
                                                 const double* Dv, double* PIL, double* PIU,
                                                 const double* NLv, const double* NUv, double* Sv,
                                                 double* Vv, double* G, double* Y) {
-    constexpr int kB = 4;
+    constexpr int kB = 8;
     double lam = 0.0;
     KktSums r{0.0, 0.0, false};
 #pragma unroll 1
