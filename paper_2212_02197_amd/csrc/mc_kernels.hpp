@@ -150,9 +150,11 @@ __device__ __noinline__ FallbackOut coop_ipm_fallback(lds_double* Hl3, int N, do
 }
 
 // Inverse-form visit of sample s: stage H, the pending BFGS update, then
-// the QP if the sample is still iterating.  A QP whose active set has not
-// settled goes to the interior-point method on W = H^-1; H_AA or W not
-// positive definite resets H = I (and diag W = 1) once.
+// the QP if the sample is still iterating (flag 2), or the Hessian shift for
+// the next OCP if its SQP has just ended (flag 4, with the update).  A QP
+// whose active set has not settled goes to the interior-point method on
+// W = H^-1; H_AA or W not positive definite resets H = I (and diag W = 1)
+// once.
 template <int NMAX>
 __device__ __forceinline__ VisitOut coop_visit_h(double* TB, double* Ws, lds_double* Wl3, int Ns_, int s,
                                               int flags, double umin, double umax, int ipm_max_iter) {
@@ -180,6 +182,11 @@ __device__ __forceinline__ VisitOut coop_visit_h(double* TB, double* Ws, lds_dou
         const int upd = coop_bfgs_h<NMAX>(Wl, Ws, Ns_, lane, si, yi, vi, wd, vo.fl);
         if (!upd) vo.skip = 1;
         if (upd && in) *wdp = wd;
+    }
+    if (flags & 4) {
+        // the shift of coop_visit_shift, on the H just updated and staged
+        const double wlast = readlane_d(wd, Ns_ - 1);
+        coop_shift_h<NMAX>(Wl, Ws, Ns_, lane, wlast, vo.fl);
     }
     if (flags & 2) {
         double d = 0.0, nl = 0.0, nu = 0.0, wdd = 0.0;
@@ -383,7 +390,8 @@ __device__ __forceinline__ KktSums adjoint_pass(int N, double alpha, const doubl
 template <int NMAX, int GMODE>
 __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, int i, const Setup& su,
                           double xhat, int lane, double* TB, double* XS, double* Wslot,
-                          double* Wl, int (&cnt)[C_NCNT], double& qfl, bool pair_ls) {
+                          double* Wl, int (&cnt)[C_NCNT], double& qfl, bool pair_ls,
+                          bool& shifted) {
     double* const U = TB + (V_U * NMAX) * 64 + lane;
     double* const G = TB + (V_G * NMAX) * 64 + lane;
     double* const Dv = TB + (V_D * NMAX) * 64 + lane;
@@ -455,7 +463,13 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
             m &= m - 1;
             const int Ns_ = __builtin_amdgcn_readlane(N, s);
             double* Ws = Wslot + (int64_t)s * NMAX * NMAX;
-            const int flags = (int)((mp >> s) & 1ull) | ((int)((ma >> s) & 1ull) << 1);
+            // a pending update without a QP is the OCP's last visit: in
+            // inverse form the Hessian shift for the next OCP joins it
+            const bool last = ((mp >> s) & 1ull) && !((ma >> s) & 1ull) && p.hess_warm &&
+                              p.qp_solver == 2;
+            const int flags = (int)((mp >> s) & 1ull) | ((int)((ma >> s) & 1ull) << 1) |
+                              (last ? 4 : 0);
+            if (last && lane == s) shifted = true;
             const VisitOut vo =
                 p.qp_solver == 2
                     ? coop_visit_h<NMAX>(TB, Ws, (lds_double*)Wl, Ns_, s, flags, p.umin, p.umax,
@@ -628,10 +642,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
                 if (out.tx) out.tx[(int64_t)i * out.S + pos] = xhat;
                 if (!isfinite(xhat) || !isfinite(P)) cnt[C_NONFIN] = 1;
             }
+            bool shifted = false;
             const bool conv = sqp_group<NMAX, GMODE>(p, step, N, i, su, xhat, lane, TB, XS, Wslot,
-                                                     Wl, cnt, qfl, wk.spw <= 32);
+                                                     Wl, cnt, qfl, wk.spw <= 32, shifted);
             if (p.hess_warm) {
-                uint64_t m = __ballot(step);
+                // samples whose last visit did not shift (no pending update)
+                uint64_t m = __ballot(step && !shifted);
                 while (m) {
                     const int s = __ffsll((unsigned long long)m) - 1;
                     m &= m - 1;
