@@ -54,7 +54,7 @@ class Params(C.Structure):
         ("n_horizon_choices", C.c_int32), ("horizon_choices", C.c_int32 * 4),
         ("L_lo", C.c_int32), ("L_hi", C.c_int32),
         ("kin_lognorm_sigma", C.c_double),
-        ("hess_warm", C.c_int32), ("pad1", C.c_int32), ("noise_scale", C.c_double),
+        ("hess_warm", C.c_int32), ("model_nx", C.c_int32), ("noise_scale", C.c_double),
     ]
 
 
@@ -95,9 +95,14 @@ def lib():
             "oc_ocp_shoot": (d, [P(Params), i32, d, pd, pd, pd]),
             "oc_ocp_grad_adjoint": (None, [P(Params), i32, pd, pd, pd, pd]),
             "oc_ocp_grad_fwd": (None, [P(Params), i32, d, pd, pd, pd]),
+            "oc_ekf3_predict": (None, [P(Params), pd, pd, d]),
+            "oc_ekf3_update": (None, [P(Params), pd, pd, d]),
+            "oc_ocp3_shoot": (d, [P(Params), i32, pd, pd, pd, pd]),
+            "oc_ocp3_grad_adjoint": (None, [P(Params), i32, pd, pd, pd, pd]),
+            "oc_ocp3_grad_fwd": (None, [P(Params), i32, pd, pd, pd, pd]),
             "oc_box_qp": (C.c_int, [i32, pd, pd, pd, pd, i32, pd, pd, pd, P(i32)]),
             "oc_bfgs_update": (C.c_int, [i32, pd, pd, pd]),
-            "oc_sqp": (C.c_int, [P(Params), i32, d, pd, pd, pd, pd, pd, i32, P(SampleOut)]),
+            "oc_sqp": (C.c_int, [P(Params), i32, pd, pd, pd, pd, pd, pd, i32, P(SampleOut)]),
             "oc_run_sample": (None, [P(Params), i64, P(SampleOut), pd, pd, pd]),
             "oc_run": (None, [P(Params), P(i64), i64, i32, P(SampleOut)]),
             "oc_stats": (None, [pd, i64, pd, pd, P(i64)]),
@@ -120,6 +125,8 @@ def params(cfg: dict) -> Params:
                 "run_ekf_for_pi", "seed", "noise_mod", "L_lo", "L_hi", "kin_lognorm_sigma",
                 "hess_warm", "noise_scale"):
         setattr(p, key, cfg[key])
+    p.model_nx = cfg.get("model_nx", 1)
+    assert p.model_nx in (1, 3)
     for a in range(3):
         p.sigma[a] = cfg["sigma"][a]
     sp_i, sp_z = cfg["sp_i"], cfg["sp_z"]
@@ -213,13 +220,39 @@ def ekf_update(cfg, x, P, y):
     return xx.value, PP.value
 
 
+def ekf3_predict(cfg, x, P, F):
+    """Three-state prediction: x (3,), P (3, 3) -> new (x, P)."""
+    p = params(cfg)
+    xx = np.array(x, dtype=np.float64).reshape(3)
+    PP = np.array(P, dtype=np.float64).reshape(9)
+    lib().oc_ekf3_predict(C.byref(p), _dp(xx), _dp(PP), F)
+    return xx, PP.reshape(3, 3)
+
+
+def ekf3_update(cfg, x, P, y):
+    p = params(cfg)
+    xx = np.array(x, dtype=np.float64).reshape(3)
+    PP = np.array(P, dtype=np.float64).reshape(9)
+    lib().oc_ekf3_update(C.byref(p), _dp(xx), _dp(PP), y)
+    return xx, PP.reshape(3, 3)
+
+
 def ocp_shoot(cfg, x0, u, zbar, want_xs=False):
+    """OCP objective from x0 (a scalar: one-state model; 3 values: three-state
+    model).  xs: the RK4 step-start states (3 per step for the three-state
+    model)."""
     p = params(cfg)
     u = np.ascontiguousarray(u, dtype=np.float64)
     zbar = np.ascontiguousarray(zbar, dtype=np.float64)
     N = len(u)
-    xs = np.zeros(N * cfg["Nc"] + 1)
-    phi = lib().oc_ocp_shoot(C.byref(p), N, x0, _dp(u), _dp(zbar), _dp(xs))
+    if np.ndim(x0) == 0:
+        xs = np.zeros(N * cfg["Nc"] + 1)
+        phi = lib().oc_ocp_shoot(C.byref(p), N, float(x0), _dp(u), _dp(zbar), _dp(xs))
+    else:
+        xv = np.ascontiguousarray(x0, dtype=np.float64).reshape(3)
+        xs = np.zeros(3 * (N * cfg["Nc"] + 1))
+        phi = lib().oc_ocp3_shoot(C.byref(p), N, _dp(xv), _dp(u), _dp(zbar), _dp(xs))
+        xs = xs.reshape(-1, 3)
     return (phi, xs) if want_xs else phi
 
 
@@ -229,9 +262,15 @@ def ocp_grad(cfg, x0, u, zbar, mode):
     zbar = np.ascontiguousarray(zbar, dtype=np.float64)
     N = len(u)
     g = np.zeros(N)
+    three = np.ndim(x0) > 0
     if mode == "adjoint":
         _, xs = ocp_shoot(cfg, x0, u, zbar, want_xs=True)
-        lib().oc_ocp_grad_adjoint(C.byref(p), N, _dp(u), _dp(zbar), _dp(xs), _dp(g))
+        xs = np.ascontiguousarray(xs.reshape(-1))
+        fn = lib().oc_ocp3_grad_adjoint if three else lib().oc_ocp_grad_adjoint
+        fn(C.byref(p), N, _dp(u), _dp(zbar), _dp(xs), _dp(g))
+    elif three:
+        xv = np.ascontiguousarray(x0, dtype=np.float64).reshape(3)
+        lib().oc_ocp3_grad_fwd(C.byref(p), N, _dp(xv), _dp(u), _dp(zbar), _dp(g))
     else:
         lib().oc_ocp_grad_fwd(C.byref(p), N, x0, _dp(u), _dp(zbar), _dp(g))
     return g
@@ -256,14 +295,18 @@ def bfgs_update(W, s, y):
 
 
 def sqp(cfg, x0, zbar, u0):
+    """One SQP solve; x0 a scalar (one-state model) or 3 values (three-state
+    model, which cfg["model_nx"] must select)."""
     p = params(cfg)
+    xv = np.array(np.atleast_1d(x0), dtype=np.float64)
+    assert len(xv) == (3 if p.model_nx == 3 else 1)
     zbar = np.ascontiguousarray(zbar, dtype=np.float64)
     u = np.array(u0, dtype=np.float64)
     N = len(u)
     pil, piu = np.zeros(N), np.zeros(N)
     cnt = SampleOut()
     W = np.zeros(N * N)
-    conv = lib().oc_sqp(C.byref(p), N, x0, _dp(zbar), _dp(u), _dp(pil), _dp(piu), _dp(W), 1,
+    conv = lib().oc_sqp(C.byref(p), N, _dp(xv), _dp(zbar), _dp(u), _dp(pil), _dp(piu), _dp(W), 1,
                         C.byref(cnt))
     return bool(conv), u, pil, piu, {f: getattr(cnt, f) for f in OUT_FIELDS[4:]}
 

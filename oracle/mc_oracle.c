@@ -338,6 +338,225 @@ void oc_ocp_grad_fwd(const oc_params *p, int32_t N, double x0, const double *u,
 }
 
 /* ------------------------------------------------------------------------
+ * Three-state model for the estimator and the OCP: the plant's eq. (CSTR)
+ * drift with the nominal kinetics (k0, Ea/R), state x = n = (n_A, n_B, n_T),
+ * output z = n_T / V.  The paper's case study uses the one-state model for
+ * both; this is the same CD-EKF and OCP at n_x = 3 (no model-plant mismatch
+ * apart from the noise and sampled kinetics).
+ * ---------------------------------------------------------------------- */
+
+/* A P + P A^T + Q, Q = diag(q), all row-major 3x3.                          */
+static void lyap3_rhs(const double A[9], const double P[9], const double q[3], double out[9])
+{
+    int a, b, c;
+    for (a = 0; a < 3; ++a)
+        for (b = 0; b < 3; ++b) {
+            double t = (a == b) ? q[a] : 0.0;
+            for (c = 0; c < 3; ++c) t += A[3 * a + c] * P[3 * c + b] + P[3 * a + c] * A[3 * b + c];
+            out[3 * a + b] = t;
+        }
+}
+
+/* CD-EKF prediction, eq. (predictionEquations) at n_x = 3: dx/dt = f3(x, F),
+ * dP/dt = A P + P A^T + F^2 diag(sigma_A^2, sigma_B^2, sigma_T^2) (the
+ * diffusion F sigma of eq. (CSTR)), A = df3/dx; classical RK4 with Nc steps
+ * on the joint (x, P) system, A evaluated at each stage.                    */
+void oc_ekf3_predict(const oc_params *p, double x[3], double P[9], double F)
+{
+    double h = p->Ts / (double)p->Nc;
+    double q[3];
+    int a, e, c;
+    for (a = 0; a < 3; ++a) q[a] = (F * p->sigma[a]) * (F * p->sigma[a]);
+    for (c = 0; c < p->Nc; ++c) {
+        double kx[4][3], kP[4][9], xs[3], Ps[9], J[9], fF[3];
+        int st;
+        static const double a_st[4] = {0.0, 0.5, 0.5, 1.0};
+        for (st = 0; st < 4; ++st) {
+            for (a = 0; a < 3; ++a) xs[a] = x[a] + (st ? a_st[st] * h * kx[st - 1][a] : 0.0);
+            for (e = 0; e < 9; ++e) Ps[e] = P[e] + (st ? a_st[st] * h * kP[st - 1][e] : 0.0);
+            oc_f3(p, p->k0, p->EaR, xs, F, kx[st]);
+            oc_f3_jac(p, p->k0, p->EaR, xs, F, J, fF);
+            lyap3_rhs(J, Ps, q, kP[st]);
+        }
+        for (a = 0; a < 3; ++a)
+            x[a] = x[a] + h / 6.0 * (kx[0][a] + 2.0 * kx[1][a] + 2.0 * kx[2][a] + kx[3][a]);
+        for (e = 0; e < 9; ++e)
+            P[e] = P[e] + h / 6.0 * (kP[0][e] + 2.0 * kP[1][e] + 2.0 * kP[2][e] + kP[3][e]);
+    }
+}
+
+/* Filtering, eq. (Josph), with g(x) = n_T / V: C = [0, 0, 1/V],
+ * R_e = R + C P C^T, K = P C^T / R_e, x += K (y - C x),
+ * P = (I - K C) P (I - K C)^T + K R K^T.                                    */
+void oc_ekf3_update(const oc_params *p, double x[3], double P[9], double y)
+{
+    double C[3] = {0.0, 0.0, 1.0 / p->V};
+    double PC[3], K[3], IKC[9], T[9], Re, e;
+    int a, b, c;
+    e = y - (C[0] * x[0] + C[1] * x[1] + C[2] * x[2]);
+    for (a = 0; a < 3; ++a) PC[a] = P[3 * a + 0] * C[0] + P[3 * a + 1] * C[1] + P[3 * a + 2] * C[2];
+    Re = p->Rmeas + C[0] * PC[0] + C[1] * PC[1] + C[2] * PC[2];
+    for (a = 0; a < 3; ++a) K[a] = PC[a] / Re;
+    for (a = 0; a < 3; ++a) x[a] = x[a] + K[a] * e;
+    for (a = 0; a < 3; ++a)
+        for (b = 0; b < 3; ++b) IKC[3 * a + b] = (a == b ? 1.0 : 0.0) - K[a] * C[b];
+    for (a = 0; a < 3; ++a)
+        for (b = 0; b < 3; ++b) {
+            double t = 0.0;
+            for (c = 0; c < 3; ++c) t += IKC[3 * a + c] * P[3 * c + b];
+            T[3 * a + b] = t;
+        }
+    for (a = 0; a < 3; ++a)
+        for (b = 0; b < 3; ++b) {
+            double t = K[a] * p->Rmeas * K[b];
+            for (c = 0; c < 3; ++c) t += T[3 * a + c] * IKC[3 * b + c];
+            P[3 * a + b] = t;
+        }
+}
+
+/* Single shooting of the OCP with the three-state model: x_{k+1} =
+ * RK4^Nc(x_k, u_k), phi = sum_k Qz (n_T,k+1 / V - zbar_k)^2 Ts.
+ * xs (may be NULL) receives the state at the start of every RK4 step
+ * (3 values each, step k Nc + c at xs[3 (k Nc + c)]) and x_N last.          */
+double oc_ocp3_shoot(const oc_params *p, int32_t N, const double x0[3], const double *u,
+                     const double *zbar, double *xs)
+{
+    double h = p->Ts / (double)p->Nc;
+    double x[3] = {x0[0], x0[1], x0[2]}, phi = 0.0;
+    int k, c, a;
+    for (k = 0; k < N; ++k) {
+        double F = u[k] / ML_MIN_PER_L_S;
+        for (c = 0; c < p->Nc; ++c) {
+            double k1[3], k2[3], k3[3], k4[3], t[3];
+            if (xs) for (a = 0; a < 3; ++a) xs[3 * (k * p->Nc + c) + a] = x[a];
+            oc_f3(p, p->k0, p->EaR, x, F, k1);
+            for (a = 0; a < 3; ++a) t[a] = x[a] + 0.5 * h * k1[a];
+            oc_f3(p, p->k0, p->EaR, t, F, k2);
+            for (a = 0; a < 3; ++a) t[a] = x[a] + 0.5 * h * k2[a];
+            oc_f3(p, p->k0, p->EaR, t, F, k3);
+            for (a = 0; a < 3; ++a) t[a] = x[a] + h * k3[a];
+            oc_f3(p, p->k0, p->EaR, t, F, k4);
+            for (a = 0; a < 3; ++a) x[a] = x[a] + h / 6.0 * (k1[a] + 2.0 * k2[a] + 2.0 * k3[a] + k4[a]);
+        }
+        {
+            double ez = x[2] / p->V - zbar[k];
+            phi += p->Qz * ez * ez * p->Ts;
+        }
+    }
+    if (xs) for (a = 0; a < 3; ++a) xs[3 * N * p->Nc + a] = x[a];
+    return phi;
+}
+
+/* y = M^T v for row-major 3x3 M.                                            */
+static void mtv3(const double M[9], const double v[3], double y[3])
+{
+    int a;
+    for (a = 0; a < 3; ++a) y[a] = M[a] * v[0] + M[3 + a] * v[1] + M[6 + a] * v[2];
+}
+
+/* y = M v for row-major 3x3 M.                                              */
+static void mv3(const double M[9], const double v[3], double y[3])
+{
+    int a;
+    for (a = 0; a < 3; ++a) y[a] = M[3 * a] * v[0] + M[3 * a + 1] * v[1] + M[3 * a + 2] * v[2];
+}
+
+/* Gradient of the three-state phi by the discrete adjoint of the RK4
+ * shooting: the adjoint vector runs backwards through every RK4 step, each
+ * stage contributing J_s^T of its adjoint; stage states recomputed from
+ * the stored step-start states.                                             */
+void oc_ocp3_grad_adjoint(const oc_params *p, int32_t N, const double *u,
+                          const double *zbar, const double *xs, double *grad)
+{
+    double h = p->Ts / (double)p->Nc;
+    double lam[3] = {0.0, 0.0, 0.0};
+    int k, c, a;
+    for (k = N - 1; k >= 0; --k) {
+        double F = u[k] / ML_MIN_PER_L_S;
+        double Fbar = 0.0;
+        {
+            double ez = xs[3 * (k + 1) * p->Nc + 2] / p->V - zbar[k];
+            lam[2] += p->Qz * 2.0 * ez * (1.0 / p->V) * p->Ts;
+        }
+        for (c = p->Nc - 1; c >= 0; --c) {
+            const double *x = xs + 3 * (k * p->Nc + c);
+            double st[4][3], kk[4][3], J[4][9], fF[4][3];
+            double kb[4][3], xb[3], sb[3];
+            static const double a_st[4] = {0.0, 0.5, 0.5, 1.0};
+            int s;
+            for (s = 0; s < 4; ++s) {
+                for (a = 0; a < 3; ++a) st[s][a] = x[a] + (s ? a_st[s] * h * kk[s - 1][a] : 0.0);
+                oc_f3(p, p->k0, p->EaR, st[s], F, kk[s]);
+                oc_f3_jac(p, p->k0, p->EaR, st[s], F, J[s], fF[s]);
+            }
+            /* x+ = x + h/6 (k1 + 2 k2 + 2 k3 + k4)                           */
+            for (a = 0; a < 3; ++a) {
+                xb[a] = lam[a];
+                kb[0][a] = lam[a] * h / 6.0;
+                kb[1][a] = lam[a] * h / 3.0;
+                kb[2][a] = lam[a] * h / 3.0;
+                kb[3][a] = lam[a] * h / 6.0;
+            }
+            /* k_s = f(x + a_s h k_{s-1}), from the last stage back           */
+            for (s = 3; s >= 0; --s) {
+                mtv3(J[s], kb[s], sb);
+                for (a = 0; a < 3; ++a) {
+                    xb[a] += sb[a];
+                    if (s > 0) kb[s - 1][a] += a_st[s] * h * sb[a];
+                }
+                Fbar += fF[s][0] * kb[s][0] + fF[s][1] * kb[s][1] + fF[s][2] * kb[s][2];
+            }
+            for (a = 0; a < 3; ++a) lam[a] = xb[a];
+        }
+        grad[k] = Fbar / ML_MIN_PER_L_S;
+    }
+}
+
+/* Gradient of the three-state phi by forward sensitivities: the tangent
+ * dx/du_j (3 values) of every j <= k is carried through each RK4 step with
+ * the stage Jacobians.                                                      */
+void oc_ocp3_grad_fwd(const oc_params *p, int32_t N, const double x0[3], const double *u,
+                      const double *zbar, double *grad)
+{
+    double h = p->Ts / (double)p->Nc;
+    double S[OC_NMAX][3];
+    double x[3] = {x0[0], x0[1], x0[2]};
+    int k, c, j, a, s;
+    static const double a_st[4] = {0.0, 0.5, 0.5, 1.0};
+    for (j = 0; j < N; ++j) { S[j][0] = S[j][1] = S[j][2] = 0.0; grad[j] = 0.0; }
+    for (k = 0; k < N; ++k) {
+        double F = u[k] / ML_MIN_PER_L_S;
+        double dF = 1.0 / ML_MIN_PER_L_S;
+        for (c = 0; c < p->Nc; ++c) {
+            double st[4][3], kk[4][3], J[4][9], fF[4][3];
+            for (s = 0; s < 4; ++s) {
+                for (a = 0; a < 3; ++a) st[s][a] = x[a] + (s ? a_st[s] * h * kk[s - 1][a] : 0.0);
+                oc_f3(p, p->k0, p->EaR, st[s], F, kk[s]);
+                oc_f3_jac(p, p->k0, p->EaR, st[s], F, J[s], fF[s]);
+            }
+            for (j = 0; j <= k; ++j) {
+                double src = (j == k) ? dF : 0.0;
+                double d[4][3], t[3], Jt[3];
+                for (s = 0; s < 4; ++s) {
+                    for (a = 0; a < 3; ++a) t[a] = S[j][a] + (s ? a_st[s] * h * d[s - 1][a] : 0.0);
+                    mv3(J[s], t, Jt);
+                    for (a = 0; a < 3; ++a) d[s][a] = Jt[a] + fF[s][a] * src;
+                }
+                for (a = 0; a < 3; ++a)
+                    S[j][a] = S[j][a] + h / 6.0 * (d[0][a] + 2.0 * d[1][a] + 2.0 * d[2][a] + d[3][a]);
+            }
+            for (a = 0; a < 3; ++a)
+                x[a] = x[a] + h / 6.0 * (kk[0][a] + 2.0 * kk[1][a] + 2.0 * kk[2][a] + kk[3][a]);
+        }
+        {
+            double ez = x[2] / p->V - zbar[k];
+            double dphidx = p->Qz * 2.0 * ez * (1.0 / p->V) * p->Ts;
+            for (j = 0; j <= k; ++j) grad[j] += dphidx * S[j][2];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------
  * Box-constrained QP subproblem of the SQP section (single shooting: no
  * equality constraints, bounds on the input step):
  *   min 1/2 d^T W d + g^T d   s.t.  lo <= d <= hi.
@@ -561,11 +780,25 @@ int oc_bfgs_update(int32_t N, double *W, const double *s, const double *y)
     return 1;
 }
 
-static void ocp_grad(const oc_params *p, int32_t N, double x0, const double *u,
+/* The OCP's objective and gradient for the model p->model_nx selects
+ * (x0: 1 or 3 values).                                                      */
+static double ocp_shoot(const oc_params *p, int32_t N, const double *x0, const double *u,
+                        const double *zbar, double *xs)
+{
+    if (p->model_nx == 3) return oc_ocp3_shoot(p, N, x0, u, zbar, xs);
+    return oc_ocp_shoot(p, N, x0[0], u, zbar, xs);
+}
+
+static void ocp_grad(const oc_params *p, int32_t N, const double *x0, const double *u,
                      const double *zbar, const double *xs, double *g)
 {
+    if (p->model_nx == 3) {
+        if (p->grad_mode == 1) oc_ocp3_grad_adjoint(p, N, u, zbar, xs, g);
+        else oc_ocp3_grad_fwd(p, N, x0, u, zbar, g);
+        return;
+    }
     if (p->grad_mode == 1) oc_ocp_grad_adjoint(p, N, u, zbar, xs, g);
-    else oc_ocp_grad_fwd(p, N, x0, u, zbar, g);
+    else oc_ocp_grad_fwd(p, N, x0[0], u, zbar, g);
 }
 
 /* ------------------------------------------------------------------------
@@ -575,16 +808,17 @@ static void ocp_grad(const oc_params *p, int32_t N, double x0, const double *u,
  * eq. (Armijo), c1 = 1e-4, beta = 0.5 -> damped BFGS.  Convergence by the
  * scaled KKT test eq. (convergence) with s_max = 100.  W^[0] = I; W reset to
  * I when the QP reports indefiniteness.  On the iteration cap the last
- * iterate is kept.  u: in = warm start, out = last iterate.  Returns 1 if
- * converged.                                                                */
-int oc_sqp(const oc_params *p, int32_t N, double x0, const double *zbar, double *u,
+ * iterate is kept.  x0: the OCP's initial state (1 or 3 values, model_nx).
+ * u: in = warm start, out = last iterate.  Returns 1 if converged.          */
+int oc_sqp(const oc_params *p, int32_t N, const double *x0, const double *zbar, double *u,
            double *pil, double *piu, double *W, int32_t reset_W, oc_sample_out *cnt)
 {
     static const double smax = 100.0;
     double g[OC_NMAX], gn[OC_NMAX], lo[OC_NMAX], hi[OC_NMAX], d[OC_NMAX];
     double nl[OC_NMAX], nu[OC_NMAX], ut[OC_NMAX], s[OC_NMAX], yv[OC_NMAX];
-    double *xs = (double *)malloc(sizeof(double) * (size_t)(N * p->Nc + 1));
-    double *xt = (double *)malloc(sizeof(double) * (size_t)(N * p->Nc + 1));
+    size_t nxs = (size_t)(N * p->Nc + 1) * (p->model_nx == 3 ? 3 : 1);
+    double *xs = (double *)malloc(sizeof(double) * nxs);
+    double *xt = (double *)malloc(sizeof(double) * nxs);
     double f;
     int i, j, l, converged = 0;
 
@@ -596,7 +830,7 @@ int oc_sqp(const oc_params *p, int32_t N, double x0, const double *zbar, double 
         if (reset_W)
             for (j = 0; j < N; ++j) W[i * N + j] = (i == j) ? 1.0 : 0.0;
     }
-    f = oc_ocp_shoot(p, N, x0, u, zbar, xs);
+    f = ocp_shoot(p, N, x0, u, zbar, xs);
     ocp_grad(p, N, x0, u, zbar, xs, g);
     cnt->grad_evals++;
     cnt->ls_trials++;
@@ -636,7 +870,7 @@ int oc_sqp(const oc_params *p, int32_t N, double x0, const double *zbar, double 
         for (bt = 0;; ++bt) {
             double ft;
             for (i = 0; i < N; ++i) ut[i] = u[i] + alpha * d[i];
-            ft = oc_ocp_shoot(p, N, x0, ut, zbar, xt);
+            ft = ocp_shoot(p, N, x0, ut, zbar, xt);
             cnt->ls_trials++;
             /* a predicted decrease below the merit's resolution cannot be
              * tested in floating point: the full step is taken             */
@@ -669,6 +903,7 @@ typedef struct {
     int32_t kind, N, L, istep;
     double sign, k0, EaR;
     double n0[3], xhat0, ubar;      /* ubar in L/s */
+    double xhat3[3];                /* three-state estimator's x-hat_0      */
 } oc_setup;
 
 static uint32_t id32(int64_t id) { return (uint32_t)id; }
@@ -717,6 +952,9 @@ static void sample_setup(const oc_params *p, int64_t sample_id, oc_setup *su)
             su->n0[1] = p->cBin * p->V;
             su->n0[2] = p->cTin * p->V;
             su->xhat0 = p->cTin * p->V;
+            su->xhat3[0] = su->n0[0];
+            su->xhat3[1] = su->n0[1];
+            su->xhat3[2] = su->n0[2];
         } else {
             double nb[4];
             oc_normal_pair(p->seed, 0, 0, id32(su->noise_id), TAG_X0, nr);
@@ -725,6 +963,9 @@ static void sample_setup(const oc_params *p, int64_t sample_id, oc_setup *su)
             su->n0[1] = nss[1] * (1.0 + p->x0_rel_std * nr[1]);
             su->n0[2] = nss[2] * (1.0 + p->x0_rel_std * nb[0]);
             su->xhat0 = nss[2];
+            su->xhat3[0] = nss[0];
+            su->xhat3[1] = nss[1];
+            su->xhat3[2] = nss[2];
         }
     }
 }
@@ -741,6 +982,7 @@ void oc_run_sample(const oc_params *p, int64_t sample_id, oc_sample_out *out,
 {
     oc_setup su;
     double n[3], xhat, P, Fprev, Ihat = 0.0, phiacc = 0.0;
+    double xh3[3], P3[9];            /* three-state estimator (model_nx 3)   */
     double ws[OC_NMAX], u[OC_NMAX], zb[OC_NMAX], pil[OC_NMAX], piu[OC_NMAX];
     double Wh[OC_NMAX * OC_NMAX];
     /* PI tangent w.r.t. theta = (Kc, tau_i) with kP = Kc, kI = Kc / tau_i:
@@ -764,6 +1006,11 @@ void oc_run_sample(const oc_params *p, int64_t sample_id, oc_sample_out *out,
     for (a = 0; a < 3; ++a) { n[a] = su.n0[a]; dn[a][0] = 0.0; dn[a][1] = 0.0; }
     xhat = su.xhat0;
     P = p->P0;
+    /* three-state estimator: x-hat_0 as the one-state reading, P_0 = P0 I   */
+    for (a = 0; a < 3; ++a) {
+        xh3[a] = su.xhat3[a];
+        for (b = 0; b < 3; ++b) P3[3 * a + b] = (a == b) ? p->P0 : 0.0;
+    }
     Fprev = su.ubar;
     for (k = 0; k < su.N; ++k) ws[k] = su.ubar * ML_MIN_PER_L_S;
     out->kind = su.kind;
@@ -783,7 +1030,14 @@ void oc_run_sample(const oc_params *p, int64_t sample_id, oc_sample_out *out,
         /* measurement y_i = c_T(t_i) + v_i, v ~ N(0, R)                     */
         oc_normal_pair(p->seed, 0, (uint32_t)i, id32(su.noise_id), TAG_MEAS, xi);
         y = z + p->noise_scale * sqrtR * xi[0];
-        if (su.kind == 0 || p->run_ekf_for_pi) {
+        if ((su.kind == 0 || p->run_ekf_for_pi) && p->model_nx == 3) {
+            oc_ekf3_predict(p, xh3, P3, Fprev);
+            oc_ekf3_update(p, xh3, P3, y);
+            xhat = xh3[2];
+            for (a = 0; a < 9; ++a)
+                if (!isfinite(P3[a])) out->nonfinite = 1;
+            if (!isfinite(xh3[0]) || !isfinite(xh3[1])) out->nonfinite = 1;
+        } else if (su.kind == 0 || p->run_ekf_for_pi) {
             oc_ekf_predict(p, &xhat, &P, Fprev);
             oc_ekf_update(p, &xhat, &P, y);
         }
@@ -798,7 +1052,8 @@ void oc_run_sample(const oc_params *p, int64_t sample_id, oc_sample_out *out,
                 zb[k] = oc_setpoint(p, i + 1 + k, su.istep, su.sign);
                 u[k] = ws[k];
             }
-            if (!oc_sqp(p, su.N, xhat, zb, u, pil, piu, Wh, i == 0 || !p->hess_warm, out))
+            if (!oc_sqp(p, su.N, p->model_nx == 3 ? xh3 : &xhat, zb, u, pil, piu, Wh,
+                        i == 0 || !p->hess_warm, out))
                 out->n_ocp_fail++;
             out->n_ocp++;
             for (k = 0; k < su.N; ++k)

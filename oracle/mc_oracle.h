@@ -57,7 +57,9 @@ typedef struct {
     int32_t L_lo, L_hi;             /* L_lo < L_hi: L ~ U{L_lo..L_hi}         */
     double kin_lognorm_sigma;       /* >0: plant k0, EaR * exp(sigma xi)      */
     int32_t hess_warm;              /* 1: shifted previous W, 0: W = I per OCP */
-    int32_t pad1;
+    int32_t model_nx;               /* estimator and OCP model: 1 the one-state
+                                       model (the paper's), 3 the three-state
+                                       eq. (CSTR) model                      */
     double noise_scale;             /* 1 stochastic; 0 deterministic run (the
                                        filter keeps its R and sigma)         */
 } oc_params;
@@ -96,11 +98,19 @@ void oc_ocp_grad_adjoint(const oc_params *p, int32_t N, const double *u,
                          const double *zbar, const double *xs, double *grad);
 void oc_ocp_grad_fwd(const oc_params *p, int32_t N, double x0, const double *u,
                      const double *zbar, double *grad);
+void oc_ekf3_predict(const oc_params *p, double x[3], double P[9], double F);
+void oc_ekf3_update(const oc_params *p, double x[3], double P[9], double y);
+double oc_ocp3_shoot(const oc_params *p, int32_t N, const double x0[3], const double *u,
+                     const double *zbar, double *xs);
+void oc_ocp3_grad_adjoint(const oc_params *p, int32_t N, const double *u,
+                          const double *zbar, const double *xs, double *grad);
+void oc_ocp3_grad_fwd(const oc_params *p, int32_t N, const double x0[3], const double *u,
+                      const double *zbar, double *grad);
 int  oc_box_qp(int32_t N, const double *W, const double *g, const double *lo,
                const double *hi, int32_t max_iter, double *d, double *nl, double *nu,
                int32_t *iters);
 int  oc_bfgs_update(int32_t N, double *W, const double *s, const double *y);
-int  oc_sqp(const oc_params *p, int32_t N, double x0, const double *zbar, double *u,
+int  oc_sqp(const oc_params *p, int32_t N, const double *x0, const double *zbar, double *u,
             double *pil, double *piu, double *W, int32_t reset_W, oc_sample_out *cnt);
 void oc_run_sample(const oc_params *p, int64_t sample_id, oc_sample_out *out,
                    double *traj_z, double *traj_u, double *traj_xhat);

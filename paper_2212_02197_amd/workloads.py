@@ -52,6 +52,7 @@ BASE = dict(
     qp_solver=2,                   # 2 inverse form, 1 active set on W, 0 interior point on W
     chunk_samples=0,               # > 0: chunked run, one captured graph replay per chunk
     cu_limit=0,                    # > 0: plan for this many compute units (CU-masked stream)
+    model_nx=1,                    # NMPC/EKF model: 1 the paper's one-state, 3 the three-state
 )
 
 
