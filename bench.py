@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--tune-intervals", type=int, default=6)
     ap.add_argument("--cu-scaling", action="store_true",
                     help="also measure NMPC throughput against compute units (CU-masked streams)")
+    ap.add_argument("--model-nx", type=int, default=1, choices=(1, 3),
+                    help="estimator / OCP model: 1 the paper's one-state model, 3 the three-state model")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain elementwise copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -116,7 +118,7 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: {n * 8} bytes read and written")
         del a, b
-    cfg = workloads.CONFIGS[args.config]()
+    cfg = workloads.CONFIGS[args.config](model_nx=args.model_nx)
     if args.samples:
         cfg["n_samples"] = args.samples
         if cfg["kind_split"] >= 0:
@@ -162,12 +164,13 @@ def main():
         roofline = dict(bound="alu", achieved=round(achieved, 4),
                         peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
                         frac=round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5),
-                        traffic=measured_traffic() if args.config == "c1" and not args.samples else None)
+                        traffic=measured_traffic()
+                        if args.config == "c1" and not args.samples and args.model_nx == 1 else None)
     camp_flops = stats["flops_algorithmic"]
     camp.close()
 
     plain = None
-    if not args.no_plain and n_nmpc:
+    if not args.no_plain and n_nmpc and args.model_nx == 1:
         plain = adjoint_vs_plain(cfg, args.plain_samples)
         log("adjoint vs plain done")
 
@@ -184,7 +187,8 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{args.config}: {S} samples ({n_nmpc} NMPC N={cfg['N']} + {n_pi} PI), "
                                f"L={cfg['L']}, Ns={cfg['Ns']}, Nc={cfg['Nc']}, seed={cfg['seed']}, "
-                               f"SQP eps={cfg['sqp_eps']}, adjoint gradient",
+                               f"SQP eps={cfg['sqp_eps']}, adjoint gradient"
+                               + (", three-state estimator and OCP model" if args.model_nx == 3 else ""),
                    "samples": S, "nmpc_samples": n_nmpc, "pi_samples": n_pi},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define MC_CL_ABI_VERSION 3u
+#define MC_CL_ABI_VERSION 4u
 #define MC_CL_SPMAX 8        /* setpoint schedule levels                        */
 #define MC_CL_NMAX 64        /* largest NMPC horizon                            */
 #define MC_CL_NHIST 202      /* histogram: underflow, 200 bins, overflow        */
@@ -143,7 +143,14 @@ typedef struct {
      * device's), for runs on a stream limited to them (mc_cl_stream_create);
      * 0: all of the device's compute units.                                 */
     int32_t cu_limit;
-    int32_t reserved0;
+    /* Model of the estimator and the NMPC's OCP: 1 (the paper's case study)
+     * the one-state model x = n_T closed by the reaction invariants; 3 the
+     * three-state eq. (CSTR) drift with the nominal kinetics, x = (n_A, n_B,
+     * n_T), a 3x3 CD-EKF (eq. (predictionEquations), eq. (Josph)) with
+     * P_0 = P0 I and x-hat_0 = C_in V (x0_mode 0) or the model's steady
+     * state at zbar(0) (x0_mode 1).  Other values: EINVAL; 3 with
+     * grad_mode 0: EUNSUPPORTED (forward sensitivities are one-state only). */
+    int32_t model_nx;
 } mc_cl_params;
 
 /* Optional outputs of mc_cl_run; every pointer may be NULL.  All are device

@@ -20,7 +20,7 @@ CNT_NAMES = ["kind", "N", "L", "n_ocp", "n_ocp_fail", "sqp_iter", "ipm_iter", "l
 NCNT = len(CNT_NAMES)
 STATUS = {0: "MC_CL_OK", -1: "MC_CL_EINVAL", -2: "MC_CL_EHIP", -3: "MC_CL_ENOMEM",
           -4: "MC_CL_ESTATE", -5: "MC_CL_EUNSUPPORTED"}
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 
 class Params(C.Structure):
@@ -52,7 +52,7 @@ class Params(C.Structure):
         ("noise_scale", C.c_double),
         ("ckpt_interval", C.c_int32), ("samples_per_wave", C.c_int32),
         ("qp_solver", C.c_int32), ("chunk_samples", C.c_int32),
-        ("cu_limit", C.c_int32), ("reserved0", C.c_int32),
+        ("cu_limit", C.c_int32), ("model_nx", C.c_int32),
     ]
 
 
@@ -150,6 +150,7 @@ def params(cfg: dict) -> Params:
     p.qp_solver = cfg.get("qp_solver", 2)
     p.chunk_samples = cfg.get("chunk_samples", 0)
     p.cu_limit = cfg.get("cu_limit", 0)
+    p.model_nx = cfg.get("model_nx", 1)
     for a in range(3):
         p.sigma[a] = cfg["sigma"][a]
     sp_i, sp_z = cfg["sp_i"], cfg["sp_z"]

@@ -82,43 +82,55 @@ struct NmpcClass {
     size_t cap_tiles = 0, cap_xs = 0, cap_W = 0;   // allocated elements
 };
 
-template <int NMAX, int GMODE>
+template <int NMAX, int GMODE, int NX>
 hipError_t launch_nmpc(const DevParams& dp, const NmpcWork& wk, const Outs& o, int slots,
                        hipStream_t st) {
-    hipLaunchKernelGGL((nmpc_kernel<NMAX, GMODE>), dim3(slots), dim3(64), 0, st, dp, wk, o);
+    hipLaunchKernelGGL((nmpc_kernel<NMAX, GMODE, NX>), dim3(slots), dim3(64), 0, st, dp, wk, o);
     return hipGetLastError();
 }
 
-template <int NMAX, int GMODE>
+template <int NMAX, int GMODE, int NX>
 int max_blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, nmpc_kernel<NMAX, GMODE>, 64, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, nmpc_kernel<NMAX, GMODE, NX>, 64, 0) !=
         hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
-int blocks_per_cu(int nmax, int gmode) {
-    if (gmode == 1) {
-        if (nmax == 16) return max_blocks_per_cu<16, 1>();
-        if (nmax == 32) return max_blocks_per_cu<32, 1>();
-        return max_blocks_per_cu<64, 1>();
+// Kernel variants: horizon class NMAX x gradient mode x model states; the
+// three-state model runs with the adjoint gradient only (validated).
+int blocks_per_cu(int nmax, int gmode, int nx) {
+    if (nx == 3) {
+        if (nmax == 16) return max_blocks_per_cu<16, 1, 3>();
+        if (nmax == 32) return max_blocks_per_cu<32, 1, 3>();
+        return max_blocks_per_cu<64, 1, 3>();
     }
-    if (nmax == 16) return max_blocks_per_cu<16, 0>();
-    if (nmax == 32) return max_blocks_per_cu<32, 0>();
-    return max_blocks_per_cu<64, 0>();
+    if (gmode == 1) {
+        if (nmax == 16) return max_blocks_per_cu<16, 1, 1>();
+        if (nmax == 32) return max_blocks_per_cu<32, 1, 1>();
+        return max_blocks_per_cu<64, 1, 1>();
+    }
+    if (nmax == 16) return max_blocks_per_cu<16, 0, 1>();
+    if (nmax == 32) return max_blocks_per_cu<32, 0, 1>();
+    return max_blocks_per_cu<64, 0, 1>();
 }
 
-hipError_t dispatch_nmpc(int nmax, int gmode, const DevParams& dp, const NmpcWork& wk,
+hipError_t dispatch_nmpc(int nmax, int gmode, int nx, const DevParams& dp, const NmpcWork& wk,
                          const Outs& o, int slots, hipStream_t st) {
-    if (gmode == 1) {
-        if (nmax == 16) return launch_nmpc<16, 1>(dp, wk, o, slots, st);
-        if (nmax == 32) return launch_nmpc<32, 1>(dp, wk, o, slots, st);
-        return launch_nmpc<64, 1>(dp, wk, o, slots, st);
+    if (nx == 3) {
+        if (nmax == 16) return launch_nmpc<16, 1, 3>(dp, wk, o, slots, st);
+        if (nmax == 32) return launch_nmpc<32, 1, 3>(dp, wk, o, slots, st);
+        return launch_nmpc<64, 1, 3>(dp, wk, o, slots, st);
     }
-    if (nmax == 16) return launch_nmpc<16, 0>(dp, wk, o, slots, st);
-    if (nmax == 32) return launch_nmpc<32, 0>(dp, wk, o, slots, st);
-    return launch_nmpc<64, 0>(dp, wk, o, slots, st);
+    if (gmode == 1) {
+        if (nmax == 16) return launch_nmpc<16, 1, 1>(dp, wk, o, slots, st);
+        if (nmax == 32) return launch_nmpc<32, 1, 1>(dp, wk, o, slots, st);
+        return launch_nmpc<64, 1, 1>(dp, wk, o, slots, st);
+    }
+    if (nmax == 16) return launch_nmpc<16, 0, 1>(dp, wk, o, slots, st);
+    if (nmax == 32) return launch_nmpc<32, 0, 1>(dp, wk, o, slots, st);
+    return launch_nmpc<64, 0, 1>(dp, wk, o, slots, st);
 }
 
 bool is_finite(double v) { return std::isfinite(v); }
@@ -248,6 +260,8 @@ static int validate(const mc_cl_params* p) {
         return MC_CL_EINVAL;
     if (p->qp_solver < 0 || p->qp_solver > 2) return MC_CL_EINVAL;
     if (p->chunk_samples < 0 || p->cu_limit < 0) return MC_CL_EINVAL;
+    if (p->model_nx != 1 && p->model_nx != 3) return MC_CL_EINVAL;
+    if (p->model_nx == 3 && p->grad_mode != 1) return MC_CL_EUNSUPPORTED;
     if (p->sample_id_offset < 0 || p->sample_id_offset + p->n_samples > (int64_t)UINT32_MAX)
         return MC_CL_EINVAL;
     return MC_CL_OK;
@@ -260,7 +274,7 @@ static int plan_class(mc_cl_ctx* c, NmpcClass& nc, int spw) {
     nc.groups = (int)((nc.count + spw - 1) / spw);
     nc.slots = std::min(nc.groups, nc.slots_full);
     nc.tile_stride = (int64_t)V_COUNT * nc.nmax * 64;
-    nc.xs_stride = (int64_t)3 * nc.nmax * 64;
+    nc.xs_stride = (int64_t)(c->prm.model_nx == 3 ? rec_width<3>() : rec_width<1>()) * nc.nmax * 64;
     nc.w_stride = (int64_t)spw * nc.nmax * nc.nmax;
     const size_t nt = (size_t)nc.slots * nc.tile_stride;
     const size_t nx = (size_t)nc.slots * nc.xs_stride;
@@ -327,7 +341,8 @@ static int launch_step(mc_cl_ctx* c, hipStream_t st, const Outs& out, bool chunk
         NmpcWork wk{nc.d_pos, nc.count, nc.spw, nc.groups, c->d_queue + k,
                     chunk ? c->d_ctl + 1 + k : nullptr, nc.d_tiles, nc.d_xs, nc.d_W,
                     nc.tile_stride, nc.xs_stride, nc.w_stride};
-        HIPCHK(dispatch_nmpc(nc.nmax, c->prm.grad_mode, c->dp, wk, out, nc.slots, st));
+        HIPCHK(dispatch_nmpc(nc.nmax, c->prm.grad_mode, c->prm.model_nx, c->dp, wk, out, nc.slots,
+                             st));
     }
     if (ev_mid) HIPCHK(hipEventRecord(ev_mid, st));
     if (c->n_pi) {
@@ -400,6 +415,7 @@ static DevParams to_dev(const mc_cl_params& p) {
     d.ckpt_C = 0;
     d.qp_solver = p.qp_solver;
     d.L_cap = INT32_MAX;
+    d.model_nx = p.model_nx;
     return d;
 }
 
@@ -506,7 +522,7 @@ int mc_cl_create(const mc_cl_params* p, mc_cl_ctx** out) {
         nc.nmax = nmaxs[k];
         nc.count = (int64_t)v.size();
         c->n_nmpc += nc.count;
-        const int bpc = blocks_per_cu(nc.nmax, gmode);
+        const int bpc = blocks_per_cu(nc.nmax, gmode, p->model_nx);
         nc.slots_full = bpc * c->n_cu;
         int nmax_in_class = 1;
         for (int64_t q : v) nmax_in_class = std::max(nmax_in_class, Nv[q]);
@@ -711,7 +727,8 @@ int mc_cl_tune(mc_cl_ctx* c, void* hip_stream, int32_t trial_intervals, mc_cl_tu
                 NmpcWork wk{nc.d_pos, nc.count, nc.spw, nc.groups, c->d_queue + k, nullptr,
                             nc.d_tiles, nc.d_xs, nc.d_W, nc.tile_stride, nc.xs_stride,
                             nc.w_stride};
-                HIPCHK(dispatch_nmpc(nc.nmax, c->prm.grad_mode, dt, wk, out, nc.slots, st));
+                HIPCHK(dispatch_nmpc(nc.nmax, c->prm.grad_mode, c->prm.model_nx, dt, wk, out,
+                                     nc.slots, st));
                 return MC_CL_OK;
             }, ms);
             r->nmpc_ms[k][j] = ms;

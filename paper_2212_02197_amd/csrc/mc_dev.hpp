@@ -40,6 +40,7 @@ struct DevParams {
     double noise_scale;
     int ckpt_C, qp_solver;
     int L_cap;           // closed-loop intervals are cut at L_cap (trial launches)
+    int model_nx;        // estimator / OCP model: 1 one-state closure, 3 three-state
 };
 
 // Noise streams: the counter's last word.
@@ -210,6 +211,126 @@ __device__ __forceinline__ void ekf_update(const DevParams& p, double& x, double
     P = IKC * P * IKC + K * p.Rmeas * K;
 }
 
+// ------------------------------------------------ three-state model ---
+// Estimator / OCP model at n_x = 3: eq. (CSTR)'s drift with the nominal
+// kinetics; with kDeriv also J = df/dn (row-major) and df/dF.
+template <bool kDeriv>
+__device__ __forceinline__ void model_f3(const DevParams& p, const double n[3], double F,
+                                         double f[3], double J[9], double fF[3]) {
+    const double iV = 1.0 / p.V;
+    const double cA = n[0] * iV, cB = n[1] * iV, cT = n[2] * iV;
+    const double icT = rcp_pos(cT);
+    const double k = p.k0 * exp(-p.EaR * icT);
+    const double rV = k * cA * cB * p.V;
+    const double eA = p.cAin - cA, eB = p.cBin - cB, eT = p.cTin - cT;
+    f[0] = eA * F - rV;
+    f[1] = eB * F - 2.0 * rV;
+    f[2] = eT * F + p.beta * rV;
+    if (kDeriv) {
+        // d(r V)/dn = (k c_B, k c_A, r V (Ea/R) / (c_T^2 V))
+        const double g0 = k * cB, g1 = k * cA, g2 = rV * p.EaR * icT * icT * iV;
+        const double dg = -F * iV;
+        J[0] = dg - g0;       J[1] = -g1;               J[2] = -g2;
+        J[3] = -2.0 * g0;     J[4] = dg - 2.0 * g1;     J[5] = -2.0 * g2;
+        J[6] = p.beta * g0;   J[7] = p.beta * g1;       J[8] = dg + p.beta * g2;
+        fF[0] = eA;
+        fF[1] = eB;
+        fF[2] = eT;
+    }
+}
+
+// Symmetric 3x3 stored as (00, 01, 02, 11, 12, 22).
+__device__ __forceinline__ double sym3(const double P[6], int a, int b) {
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    return P[lo == 0 ? hi : (lo == 1 ? 2 + hi : 5)];
+}
+
+// o = J P + P J^T + diag(q) for symmetric P (= M + M^T + diag(q), M = J P).
+__device__ __forceinline__ void lyap3(const double J[9], const double P[6], const double q[3],
+                                      double o[6]) {
+    double M[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            M[3 * a + b] = J[3 * a] * sym3(P, 0, b) + J[3 * a + 1] * sym3(P, 1, b) +
+                           J[3 * a + 2] * sym3(P, 2, b);
+    o[0] = 2.0 * M[0] + q[0];
+    o[1] = M[1] + M[3];
+    o[2] = M[2] + M[6];
+    o[3] = 2.0 * M[4] + q[1];
+    o[4] = M[5] + M[7];
+    o[5] = 2.0 * M[8] + q[2];
+}
+
+// CD-EKF prediction at n_x = 3, eq. (predictionEquations): RK4 with Nc steps
+// on (x, P), dP/dt = J P + P J^T + F^2 diag(sigma^2), J at every stage.
+__device__ __forceinline__ void ekf3_predict(const DevParams& p, double x[3], double P[6],
+                                             double F) {
+    const double h = p.Ts / (double)p.Nc;
+    const double h6 = h / 6.0;
+    const double q[3] = {(F * p.sig[0]) * (F * p.sig[0]), (F * p.sig[1]) * (F * p.sig[1]),
+                         (F * p.sig[2]) * (F * p.sig[2])};
+#pragma unroll 1
+    for (int c = 0; c < p.Nc; ++c) {
+        double kx[3], kP[6], J[9], fF[3], ax[3], aP[6];
+        model_f3<true>(p, x, F, kx, J, fF);
+        lyap3(J, P, q, kP);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ax[a] = kx[a];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) aP[e] = kP[e];
+#pragma unroll
+        for (int st = 1; st < 4; ++st) {
+            const double cs = st == 3 ? h : 0.5 * h;
+            const double w = st == 3 ? 1.0 : 2.0;
+            double sx[3], sP[6];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) sx[a] = x[a] + cs * kx[a];
+#pragma unroll
+            for (int e = 0; e < 6; ++e) sP[e] = P[e] + cs * kP[e];
+            model_f3<true>(p, sx, F, kx, J, fF);
+            lyap3(J, sP, q, kP);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) ax[a] += w * kx[a];
+#pragma unroll
+            for (int e = 0; e < 6; ++e) aP[e] += w * kP[e];
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x[a] += h6 * ax[a];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) P[e] += h6 * aP[e];
+    }
+}
+
+// Filtering with the Joseph form, eq. (Josph), C = [0, 0, 1/V]:
+// K = P C^T / (R + C P C^T), x += K (y - C x),
+// P = (I - K C) P (I - K C)^T + K R K^T.
+__device__ __forceinline__ void ekf3_update(const DevParams& p, double x[3], double P[6],
+                                            double y) {
+    const double C = 1.0 / p.V;
+    const double e = y - x[2] * C;
+    const double pc[3] = {P[2] * C, P[4] * C, P[5] * C};
+    const double iRe = 1.0 / (p.Rmeas + C * pc[2]);
+    const double K[3] = {pc[0] * iRe, pc[1] * iRe, pc[2] * iRe};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a] += K[a] * e;
+    // T = (I - K C) P: T_ab = P_ab - K_a C P_2b
+    double T[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) T[3 * a + b] = sym3(P, a, b) - K[a] * pc[b];
+    // P_ab = T_ab - T_a2 C K_b + R K_a K_b
+    const double R = p.Rmeas;
+    P[0] = T[0] - T[2] * C * K[0] + R * K[0] * K[0];
+    P[1] = T[1] - T[2] * C * K[1] + R * K[0] * K[1];
+    P[2] = T[2] - T[2] * C * K[2] + R * K[0] * K[2];
+    P[3] = T[4] - T[5] * C * K[1] + R * K[1] * K[1];
+    P[4] = T[5] - T[5] * C * K[2] + R * K[1] * K[2];
+    P[5] = T[8] - T[8] * C * K[2] + R * K[2] * K[2];
+}
+
 // --------------------------------------------------------- sample set-up ---
 struct Setup {
     uint32_t nid;       // noise id
@@ -345,6 +466,125 @@ __device__ __forceinline__ double ocp_shoot(const DevParams& p, int N, double x0
             r[0] = A;
             r[kTile] = B / kMlMinPerLs;
             r[2 * kTile] = p.Qz * 2.0 * ez * iV * p.Ts;
+        }
+    }
+    return phi;
+}
+
+// Record width of one control interval: the one-state model keeps
+// (A_k, B_k, c_k), the three-state model A_k (3x3, row-major), B_k (3) and
+// the one non-zero entry of c_k (the stage cost depends on n_T only).
+template <int NX>
+constexpr int rec_width() { return NX == 3 ? 13 : 3; }
+
+// ocp_shoot with the three-state model from x0 (3 values).  With kRec, for
+// every interval k the record rec[(13 k + j) kTile] holds
+//   j = 0..8:  A_k = dx_{k+1}/dx_k (row-major),
+//   j = 9..11: B_k = dx_{k+1}/du_k (per mL/min),
+//   j = 12:    c_k = d(stage cost at x_{k+1})/dn_{T,k+1}.
+// The tangents of x_k and of F are carried through every RK4 stage beside
+// the state (J_s times the stage's tangent), the form of the forward pass.
+template <bool kRec>
+__device__ __forceinline__ double ocp_shoot3(const DevParams& p, int N, const double (&x0)[3],
+                                             int i0, int istep, double sign, const double* u,
+                                             const double* d, double alpha, bool use_d,
+                                             double* rec) {
+    const double h = p.Ts / (double)p.Nc;
+    const double h2 = 0.5 * h, h6 = h / 6.0;
+    const double iV = 1.0 / p.V;
+    double x[3] = {x0[0], x0[1], x0[2]};
+    double phi = 0.0;
+    double un = u[0], dn = use_d ? d[0] : 0.0;
+#pragma unroll 1
+    for (int k = 0; k < N; ++k) {
+        double uk = un;
+        if (use_d) uk = uk + alpha * dn;
+        if (k + 1 < N) {
+            un = u[(k + 1) * kTile];
+            if (use_d) dn = d[(k + 1) * kTile];
+        }
+        const double F = uk / kMlMinPerLs;
+        double A[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
+        double B[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+        for (int c = 0; c < p.Nc; ++c) {
+            if (kRec) {
+                double kx[3], J[9], fF[3], ax[3], aA[9], aB[3], dA[9], dB[3];
+                model_f3<true>(p, x, F, kx, J, fF);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+#pragma unroll
+                    for (int b = 0; b < 3; ++b)
+                        dA[3 * a + b] = J[3 * a] * A[b] + J[3 * a + 1] * A[3 + b] +
+                                        J[3 * a + 2] * A[6 + b];
+                    dB[a] = J[3 * a] * B[0] + J[3 * a + 1] * B[1] + J[3 * a + 2] * B[2] + fF[a];
+                    ax[a] = kx[a];
+                    aB[a] = dB[a];
+                }
+#pragma unroll
+                for (int e = 0; e < 9; ++e) aA[e] = dA[e];
+#pragma unroll
+                for (int st = 1; st < 4; ++st) {
+                    const double cs = st == 3 ? h : h2;
+                    const double w = st == 3 ? 1.0 : 2.0;
+                    double sx[3], sA[9], sB[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        sx[a] = x[a] + cs * kx[a];
+                        sB[a] = B[a] + cs * dB[a];
+                    }
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) sA[e] = A[e] + cs * dA[e];
+                    model_f3<true>(p, sx, F, kx, J, fF);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+                        for (int b = 0; b < 3; ++b)
+                            dA[3 * a + b] = J[3 * a] * sA[b] + J[3 * a + 1] * sA[3 + b] +
+                                            J[3 * a + 2] * sA[6 + b];
+                        dB[a] = J[3 * a] * sB[0] + J[3 * a + 1] * sB[1] + J[3 * a + 2] * sB[2] +
+                                fF[a];
+                        ax[a] += w * kx[a];
+                        aB[a] += w * dB[a];
+                    }
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) aA[e] += w * dA[e];
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    x[a] += h6 * ax[a];
+                    B[a] += h6 * aB[a];
+                }
+#pragma unroll
+                for (int e = 0; e < 9; ++e) A[e] += h6 * aA[e];
+            } else {
+                double kx[3], ax[3], sx[3], J[9], fF[3];
+                model_f3<false>(p, x, F, kx, J, fF);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) ax[a] = kx[a];
+#pragma unroll
+                for (int st = 1; st < 4; ++st) {
+                    const double cs = st == 3 ? h : h2;
+                    const double w = st == 3 ? 1.0 : 2.0;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) sx[a] = x[a] + cs * kx[a];
+                    model_f3<false>(p, sx, F, kx, J, fF);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) ax[a] += w * kx[a];
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a) x[a] += h6 * ax[a];
+            }
+        }
+        const double ez = x[2] * iV - setpoint(p, i0 + 1 + k, istep, sign);
+        phi += p.Qz * ez * ez * p.Ts;
+        if (kRec) {
+            double* const r = rec + (int64_t)(13 * k) * kTile;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) r[e * kTile] = A[e];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) r[(9 + a) * kTile] = B[a] / kMlMinPerLs;
+            r[12 * kTile] = p.Qz * 2.0 * ez * iV * p.Ts;
         }
     }
     return phi;

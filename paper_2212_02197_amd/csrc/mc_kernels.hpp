@@ -87,14 +87,19 @@ __device__ __forceinline__ int wave_max_i(int v) {
 // per active-set solve m^3/3 + 2 m^2 + 2 N m + 6 N, BFGS 6 N^2 + 23 N per
 // applied update (9 N if skipped), shift 3 N^2, inversion for the
 // interior-point fallback 7 N^3 / 3; interior-point iterations as above.
+// With the three-state model (nx = 3; model evaluation 21, its Jacobian 16
+// more): EKF interval 490 Nc + 80, shooting 126 N Nc + 9 N per trial,
+// adjoint gradient 520 N Nc + 28 N (the interval tangents carried through
+// the RK4 stages and the reverse sweep with A_k^T).
 __device__ __forceinline__ double sample_flops(const DevParams& p, int kind, int N, int L,
-                                               const int (&c)[C_NCNT], int gmode, double coop) {
+                                               const int (&c)[C_NCNT], int gmode, double coop,
+                                               int nx) {
     const double Ns = p.Ns, Nc = p.Nc, n = N, l = L;
     double fl = 3.0 * (l + 1.0) + l * (8.0 + 52.0 * Ns);
-    if (kind == 0 || p.run_ekf_for_pi) fl += l * (142.0 * Nc + 12.0);
+    if (kind == 0 || p.run_ekf_for_pi) fl += l * (nx == 3 ? 490.0 * Nc + 80.0 : 142.0 * Nc + 12.0);
     if (kind == 1) return fl + 10.0 * l;
-    const double shoot = 73.0 * n * Nc + 9.0 * n;
-    const double grad = gmode == 1 ? 78.0 * n * Nc + 9.0 * n
+    const double shoot = nx == 3 ? 126.0 * n * Nc + 9.0 * n : 73.0 * n * Nc + 9.0 * n;
+    const double grad = gmode == 1 ? (nx == 3 ? 520.0 * n * Nc + 28.0 * n : 78.0 * n * Nc + 9.0 * n)
                                    : 117.0 * n * Nc + 13.0 * Nc * n * (n + 1.0) + n * (n + 1.0) + 6.0 * n;
     const double ipm = n * n * n / 3.0 + 7.0 * n * n + 60.0 * n;
     const double asi = n * n * n / 3.0 + 6.0 * n * n + 10.0 * n;
@@ -384,12 +389,95 @@ __device__ __forceinline__ KktSums adjoint_pass(int N, double alpha, const doubl
     return r;
 }
 
+// adjoint_pass for the three-state record (ocp_shoot3): mu = lambda_{k+1} +
+// c_k e_T, g_k = B_k . mu, lambda_k = A_k^T mu; the same fused step update
+// and KKT sums.  The records of 4 intervals are loaded together.
+template <bool kUpdate>
+__device__ __forceinline__ KktSums adjoint_pass3(int N, double alpha, const double* rec, double* U,
+                                                 const double* Dv, double* PIL, double* PIU,
+                                                 const double* NLv, const double* NUv, double* Sv,
+                                                 double* Vv, double* G, double* Y) {
+    constexpr int kB = 4;
+    double l0 = 0.0, l1 = 0.0, l2 = 0.0;
+    KktSums r{0.0, 0.0, false};
+#pragma unroll 1
+    for (int top = N - 1; top >= 0; top -= kB) {
+        double R[kB][13], G0[kB], u[kB], dv[kB], pl[kB], pu[kB], nl[kB], nu[kB], vv[kB];
+#pragma unroll
+        for (int j = 0; j < kB; ++j) {
+            const int k = top - j >= 0 ? top - j : 0;
+            const double* const rr = rec + (int64_t)(13 * k) * kTile;
+#pragma unroll
+            for (int e = 0; e < 13; ++e) R[j][e] = rr[e * kTile];
+            if (kUpdate) {
+                G0[j] = G[k * 64];
+                u[j] = U[k * 64];
+                dv[j] = Dv[k * 64];
+                pl[j] = PIL[k * 64];
+                pu[j] = PIU[k * 64];
+                nl[j] = NLv[k * 64];
+                nu[j] = NUv[k * 64];
+                vv[j] = Vv[k * 64];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kB; ++j) {
+            const int k = top - j;
+            if (k >= 0) {
+                const double m0 = l0, m1 = l1, m2 = l2 + R[j][12];
+                const double gk = R[j][9] * m0 + R[j][10] * m1 + R[j][11] * m2;
+                l0 = R[j][0] * m0 + R[j][3] * m1 + R[j][6] * m2;
+                l1 = R[j][1] * m0 + R[j][4] * m1 + R[j][7] * m2;
+                l2 = R[j][2] * m0 + R[j][5] * m1 + R[j][8] * m2;
+                double p_l = 0.0, p_u = 0.0;
+                if (kUpdate) {
+                    const double un = u[j] + alpha * dv[j];
+                    Sv[k * 64] = un - u[j];
+                    U[k * 64] = un;
+                    p_l = pl[j] + alpha * (nl[j] - pl[j]);
+                    p_u = pu[j] + alpha * (nu[j] - pu[j]);
+                    PIL[k * 64] = p_l;
+                    PIU[k * 64] = p_u;
+                    Vv[k * 64] = alpha * vv[j];
+                    Y[k * 64] = gk - G0[j];
+                }
+                G[k * 64] = gk;
+                kkt_add(r, gk, p_l, p_u);
+            }
+        }
+    }
+    return r;
+}
+
+// The shooting pass and the gradient pass of the estimator's model.
+template <int NX, bool kRec>
+__device__ __forceinline__ double shoot_nx(const DevParams& p, int N, const double (&x0)[NX],
+                                           int i0, int istep, double sign, const double* u,
+                                           const double* d, double alpha, bool use_d,
+                                           double* rec) {
+    if constexpr (NX == 3)
+        return ocp_shoot3<kRec>(p, N, x0, i0, istep, sign, u, d, alpha, use_d, rec);
+    else
+        return ocp_shoot<kRec>(p, N, x0[0], i0, istep, sign, u, d, alpha, use_d, rec);
+}
+
+template <int NX, bool kUpdate>
+__device__ __forceinline__ KktSums adjoint_nx(int N, double alpha, const double* rec, double* U,
+                                              const double* Dv, double* PIL, double* PIU,
+                                              const double* NLv, const double* NUv, double* Sv,
+                                              double* Vv, double* G, double* Y) {
+    if constexpr (NX == 3)
+        return adjoint_pass3<kUpdate>(N, alpha, rec, U, Dv, PIL, PIU, NLv, NUv, Sv, Vv, G, Y);
+    else
+        return adjoint_pass<kUpdate>(N, alpha, rec, U, Dv, PIL, PIU, NLv, NUv, Sv, Vv, G, Y);
+}
+
 // One SQP solve (SQP section, single shooting) for every lane with `live`;
 // returns per lane whether it converged.  u (V_U) holds the warm start on
 // entry and the last iterate on return.
-template <int NMAX, int GMODE>
+template <int NMAX, int GMODE, int NX>
 __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, int i, const Setup& su,
-                          double xhat, int lane, double* TB, double* XS, double* Wslot,
+                          const double (&xhat)[NX], int lane, double* TB, double* XS, double* Wslot,
                           double* Wl, int (&cnt)[C_NCNT], double& qfl, bool pair_ls,
                           bool& shifted) {
     double* const U = TB + (V_U * NMAX) * 64 + lane;
@@ -405,6 +493,7 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
     double* const Vv = TB + (V_V * NMAX) * 64 + lane;
     double* const Xs = XS + lane;
     static constexpr double smax = 100.0;
+    static_assert(GMODE == 1 || NX == 1, "forward sensitivities: one-state model only");
 
     double f = 0.0;
     if (live) {
@@ -433,12 +522,12 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
     KktSums ks{0.0, 0.0, false};   // sums of the next KKT test
     double Dl = 0.0;               // g'd of the last QP step
     if (live) {
-        f = ocp_shoot<GMODE == 1>(p, N, xhat, i, su.istep, su.sign, U, Dv, 0.0, false, Xs);
+        f = shoot_nx<NX, GMODE == 1>(p, N, xhat, i, su.istep, su.sign, U, Dv, 0.0, false, Xs);
         cnt[C_LS]++;
-        if (GMODE == 1)
-            ks = adjoint_pass<false>(N, 0.0, Xs, U, Dv, PIL, PIU, NLv, NUv, Sv, Vv, G, Yv);
+        if constexpr (GMODE == 1)
+            ks = adjoint_nx<NX, false>(N, 0.0, Xs, U, Dv, PIL, PIU, NLv, NUv, Sv, Vv, G, Yv);
         else
-            ks = ocp_grad_fwd<NMAX>(p, N, xhat, i, su.istep, su.sign, U, G, nullptr, Dv, PIL, PIU);
+            ks = ocp_grad_fwd<NMAX>(p, N, xhat[0], i, su.istep, su.sign, U, G, nullptr, Dv, PIL, PIU);
         cnt[C_GRAD]++;
     }
     bool active = live, pending = false, converged = false;
@@ -505,7 +594,9 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
             const int src = lane & 31;
             const bool partner = lane >= 32;
             const int Np = __shfl(N, src, 64);
-            const double xp = __shfl(xhat, src, 64);
+            double xp[NX];
+#pragma unroll
+            for (int a = 0; a < NX; ++a) xp[a] = __shfl(xhat[a], src, 64);
             const int isp = __shfl(su.istep, src, 64);
             const double sgp = __shfl(su.sign, src, 64);
             double* const Up = TB + (V_U * NMAX) * 64 + src;
@@ -519,7 +610,7 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
                 const double my_a = partner ? p.ls_beta * a_o : a_o;
                 double ft = 0.0;
                 if (s_on && my_bt <= p.ls_max_bt)
-                    ft = ocp_shoot<GMODE == 1>(p, Np, xp, i, isp, sgp, Up, Dp, my_a, true, Xs);
+                    ft = shoot_nx<NX, GMODE == 1>(p, Np, xp, i, isp, sgp, Up, Dp, my_a, true, Xs);
                 const double ft2 = __shfl(ft, (lane + 32) & 63, 64);
                 if (!partner && searching) {
                     cnt[C_LS]++;
@@ -553,7 +644,7 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
             while (__ballot(searching)) {
                 if (searching) {
                     const double ft =
-                        ocp_shoot<GMODE == 1>(p, N, xhat, i, su.istep, su.sign, U, Dv, alpha, true, Xs);
+                        shoot_nx<NX, GMODE == 1>(p, N, xhat, i, su.istep, su.sign, U, Dv, alpha, true, Xs);
                     cnt[C_LS]++;
                     bool accept = false;
                     if (bt == 0 && -D <= 64.0 * DBL_EPSILON * (1.0 + fabs(f))) accept = true;
@@ -565,8 +656,9 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
             }
         }
         if (active) {
-            if (GMODE == 1) {
-                ks = adjoint_pass<true>(N, alpha, Xs + rec_off, U, Dv, PIL, PIU, NLv, NUv, Sv, Vv, G, Yv);
+            if constexpr (GMODE == 1) {
+                ks = adjoint_nx<NX, true>(N, alpha, Xs + rec_off, U, Dv, PIL, PIU, NLv, NUv, Sv, Vv, G,
+                                          Yv);
             } else {
                 #pragma unroll 4
                 for (int k = 0; k < N; ++k) {
@@ -578,7 +670,7 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
                     PIU[k * 64] = PIU[k * 64] + alpha * (NUv[k * 64] - PIU[k * 64]);
                     Vv[k * 64] = alpha * Vv[k * 64];
                 }
-                ks = ocp_grad_fwd<NMAX>(p, N, xhat, i, su.istep, su.sign, U, G, Yv, Dv, PIL, PIU);
+                ks = ocp_grad_fwd<NMAX>(p, N, xhat[0], i, su.istep, su.sign, U, G, Yv, Dv, PIL, PIU);
             }
             cnt[C_GRAD]++;
             pending = true;
@@ -588,7 +680,7 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
     return converged;
 }
 
-template <int NMAX, int GMODE>
+template <int NMAX, int GMODE, int NX>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVES_PER_EU))) void nmpc_kernel(DevParams p, NmpcWork wk, Outs out) {
     // staged W (or H) of one sample, then two broadcast vectors (lds_vec)
     __shared__ __attribute__((aligned(16))) double Wl[NMAX * NMAX + 2 * NMAX];
@@ -618,7 +710,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
         for (int c = 0; c < C_NCNT; ++c) cnt[c] = 0;
         double qfl = 0.0;   // inverse-form QP / BFGS / shift work of this lane's sample
         double n[3] = {su.n0[0], su.n0[1], su.n0[2]};
-        double xhat = su.xhat0, P = p.P0, Fprev = su.ubar, phiacc = 0.0;
+        // estimator state: x-hat (NX values) and P (1, or the 6 entries of
+        // the symmetric 3x3 with P_0 = P0 I)
+        double xhat[NX], P[NX == 3 ? 6 : 1];
+        if constexpr (NX == 3) {
+            if (p.x0_mode == 0) {
+                xhat[0] = p.cAin * p.V;
+                xhat[1] = p.cBin * p.V;
+                xhat[2] = p.cTin * p.V;
+            } else {
+                // the model's steady state at zbar(0), as for the one-state filter
+                const double T = setpoint(p, 0, su.istep, su.sign);
+                xhat[0] = (p.cAin + (p.cTin - T) / p.beta) * p.V;
+                xhat[1] = (p.cBin + 2.0 * (p.cTin - T) / p.beta) * p.V;
+                xhat[2] = T * p.V;
+            }
+            P[0] = p.P0; P[1] = 0.0; P[2] = 0.0; P[3] = p.P0; P[4] = 0.0; P[5] = p.P0;
+        } else {
+            xhat[0] = su.xhat0;
+            P[0] = p.P0;
+        }
+        double Fprev = su.ubar, phiacc = 0.0;
         uint64_t hsh = 14695981039346656037ull;
         if (has)
             #pragma unroll 1
@@ -637,13 +749,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
             if (step) {
                 const double y = z + p.noise_scale * sqrtR *
                                          normal_first(p.seed, 0, (uint32_t)i, su.nid, kTagMeas);
-                ekf_predict(p, xhat, P, Fprev);
-                ekf_update(p, xhat, P, y);
-                if (out.tx) out.tx[(int64_t)i * out.S + pos] = xhat;
-                if (!isfinite(xhat) || !isfinite(P)) cnt[C_NONFIN] = 1;
+                bool fin = true;
+                if constexpr (NX == 3) {
+                    ekf3_predict(p, xhat, P, Fprev);
+                    ekf3_update(p, xhat, P, y);
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) fin = fin && isfinite(P[e]);
+                } else {
+                    ekf_predict(p, xhat[0], P[0], Fprev);
+                    ekf_update(p, xhat[0], P[0], y);
+                    fin = isfinite(P[0]);
+                }
+#pragma unroll
+                for (int a = 0; a < NX; ++a) fin = fin && isfinite(xhat[a]);
+                if (out.tx) out.tx[(int64_t)i * out.S + pos] = xhat[NX - 1];
+                if (!fin) cnt[C_NONFIN] = 1;
             }
             bool shifted = false;
-            const bool conv = sqp_group<NMAX, GMODE>(p, step, N, i, su, xhat, lane, TB, XS, Wslot,
+            const bool conv = sqp_group<NMAX, GMODE, NX>(p, step, N, i, su, xhat, lane, TB, XS, Wslot,
                                                      Wl, cnt, qfl, wk.spw <= 32, shifted);
             if (p.hess_warm) {
                 // samples whose last visit did not shift (no pending update)
@@ -692,7 +815,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
             cnt[C_KIND] = 0;
             cnt[C_N] = N;
             cnt[C_L] = L;
-            out.flops[pos] = sample_flops(p, 0, N, L, cnt, GMODE, qfl);
+            out.flops[pos] = sample_flops(p, 0, N, L, cnt, GMODE, qfl, NX);
 #pragma unroll
             for (int c = 0; c < C_NCNT; ++c) out.cnt[(int64_t)c * out.S + pos] = cnt[c];
         }
@@ -719,6 +842,19 @@ __global__ __launch_bounds__(64) void pi_kernel(DevParams p, const int64_t* pos_
     const double sqh = sqrt(h);
     double n[3] = {su.n0[0], su.n0[1], su.n0[2]};
     double xhat = su.xhat0, P = p.P0, Fprev = su.ubar, Ihat = 0.0, phiacc = 0.0;
+    // the three-state estimator, when the model is selected (x-hat_0 and
+    // P_0 = P0 I as in the NMPC kernel)
+    double x3[3] = {0.0, 0.0, 0.0}, P3[6] = {p.P0, 0.0, 0.0, p.P0, 0.0, p.P0};
+    if (p.model_nx == 3) {
+        if (p.x0_mode == 0) {
+            x3[0] = p.cAin * p.V; x3[1] = p.cBin * p.V; x3[2] = p.cTin * p.V;
+        } else {
+            const double T = setpoint(p, 0, su.istep, su.sign);
+            x3[0] = (p.cAin + (p.cTin - T) / p.beta) * p.V;
+            x3[1] = (p.cBin + 2.0 * (p.cTin - T) / p.beta) * p.V;
+            x3[2] = T * p.V;
+        }
+    }
     int nonfin = 0;
     for (int i = 0;; ++i) {
         const double z = n[2] / p.V;
@@ -735,7 +871,15 @@ __global__ __launch_bounds__(64) void pi_kernel(DevParams p, const int64_t* pos_
         }
         const double y = z + p.noise_scale * sqrtR *
                                  normal_first(p.seed, 0, (uint32_t)i, su.nid, kTagMeas);
-        if (p.run_ekf_for_pi) {
+        if (p.run_ekf_for_pi && p.model_nx == 3) {
+            ekf3_predict(p, x3, P3, Fprev);
+            ekf3_update(p, x3, P3, y);
+            xhat = x3[2];
+            bool fin = isfinite(x3[0]) && isfinite(x3[1]) && isfinite(x3[2]);
+#pragma unroll
+            for (int e = 0; e < 6; ++e) fin = fin && isfinite(P3[e]);
+            if (!fin) nonfin = 1;
+        } else if (p.run_ekf_for_pi) {
             ekf_predict(p, xhat, P, Fprev);
             ekf_update(p, xhat, P, y);
             if (!isfinite(xhat) || !isfinite(P)) nonfin = 1;
@@ -762,7 +906,7 @@ __global__ __launch_bounds__(64) void pi_kernel(DevParams p, const int64_t* pos_
     out.phi[pos] = phiacc / (double)(su.L + 1);
     out.hash[pos] = 14695981039346656037ull;
     const int vals[C_NCNT] = {1, su.N, su.L, 0, 0, 0, 0, 0, 0, 0, 0, 0, nonfin, 0, 0};
-    out.flops[pos] = sample_flops(p, 1, su.N, su.L, vals, 1, 0.0);
+    out.flops[pos] = sample_flops(p, 1, su.N, su.L, vals, 1, 0.0, p.model_nx);
 #pragma unroll
     for (int c = 0; c < C_NCNT; ++c) out.cnt[(int64_t)c * out.S + pos] = vals[c];
 }

@@ -89,10 +89,17 @@ def _create(cfg, **over):
                                   dict(n_samples=0), dict(Ns=0), dict(k0=float("nan")),
                                   dict(Ts=-1.0), dict(grad_mode=2), dict(P0=0.0),
                                   dict(sp_z=(250.0,), sp_i=(0,)), dict(kP=0.0),
-                                  dict(chunk_samples=-1), dict(cu_limit=-1)])
+                                  dict(chunk_samples=-1), dict(cu_limit=-1), dict(model_nx=2),
+                                  dict(model_nx=0)])
 def test_invalid_parameters_are_rejected_before_any_device_call(lib, over):
     from paper_2212_02197_amd import workloads
     assert _create(workloads.c0_small_nmpc(), **over) == -1
+
+
+def test_three_state_model_needs_the_adjoint_gradient(lib):
+    from paper_2212_02197_amd import workloads
+    unsupported = [k for k, v in binding.STATUS.items() if v == "MC_CL_EUNSUPPORTED"][0]
+    assert _create(workloads.c0_small_nmpc(), model_nx=3, grad_mode=0) == unsupported
 
 
 def test_struct_size_and_version_are_checked(lib):

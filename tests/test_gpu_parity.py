@@ -367,3 +367,73 @@ def test_cu_limited_stream_matches_full_device():
     np.testing.assert_array_equal(ps["ashash"], ps0["ashash"])
     ref = oracle_run(cfg)
     compare(phi, ps, ref, tag="cu16")
+
+
+# ------------------------------------------------------ three-state model ---
+# The estimator and the OCP on the three-state eq. (CSTR) model (model_nx 3):
+# same tolerances as the one-state cases.
+
+def test_three_state_c0_full():
+    # 64 NMPC samples, N = 10 (the 16-wide horizon class), perturbed
+    # steady-state starts; the model matches the plant apart from the noise
+    cfg = W.c0_small_nmpc(model_nx=3)
+    phi, stats, ps, _ = gpu_run(cfg)
+    ref = oracle_run(cfg)
+    good = compare_conditioned(cfg, phi, ps, ref, "c0-3state")
+    assert good.sum() >= 3 * len(good) // 4
+    m, v, h = oracle.stats(ref["phi"])
+    assert stats["mean"][0] == pytest.approx(m, rel=1e-6)
+
+
+def test_three_state_all_horizon_classes_and_pi_estimator():
+    # horizons 10 / 25 / 50 (all three kernel classes) with ragged lengths,
+    # then PI samples that run the three-state filter for their estimates
+    cfg = W.c3_uneven(n_samples=30, sample_id_offset=5000, model_nx=3, kin_lognorm_sigma=0.0,
+                      L_lo=20, L_hi=45)
+    phi, stats, ps, _ = gpu_run(cfg)
+    ref = oracle_run(cfg)
+    for f in ("kind", "N", "L", "n_ocp"):
+        np.testing.assert_array_equal(ps[f], ref[f], err_msg=f)
+    assert set(ps["N"].tolist()) == {10, 25, 50}
+    # the SQP stops at a scaled KKT residual of 1e-6, so in these start-up
+    # transients about half of the samples move by 1e-7..1e-6 between the
+    # oracle's own two gradient orders (bounded as in the c3 case)
+    good = compare_conditioned(cfg, phi, ps, ref, "3state classes")
+    assert good.sum() >= len(good) // 3
+
+
+def test_three_state_trajectories_and_estimates():
+    # stochastic closed loops, element by element: z, u and the filter's n_T
+    # estimate (NMPC sample 0, PI sample 1 with the three-state filter)
+    cfg = W.c1_paper_scale(n_samples=2, kind_split=1, noise_mod=1, N=20, Ns=10, L=60,
+                           sqp_eps=1e-9, model_nx=3)
+    phi, stats, ps, tr = gpu_run(cfg, traj=True)
+    for s in range(2):
+        r = oracle.run_sample(cfg, s, traj=True)
+        tol = 1e-6 if s == 0 else 1e-9
+        assert phi[s] == pytest.approx(r["phi"], rel=tol)
+        np.testing.assert_allclose(tr["z"][:, s], r["z"], rtol=tol)
+        np.testing.assert_allclose(tr["xhat"][:, s], r["xhat"], rtol=tol)
+        np.testing.assert_allclose(tr["u"][:, s], r["u"], rtol=1e-5 if s == 0 else 1e-9,
+                                   atol=1e-12)
+
+
+def test_three_state_paired_line_search_is_the_serial_one():
+    # at most 32 samples per wavefront the line search evaluates two trial
+    # steps per pass on paired lanes; 64 per wavefront is the serial search
+    cfg = W.c0_small_nmpc(n_samples=40, L=8, model_nx=3)
+    outs = []
+    for spw in (16, 64):
+        phi, stats, ps, _ = gpu_run(dict(cfg, samples_per_wave=spw))
+        outs.append((phi, ps["ashash"], ps["sqp_iter"], ps["ls_trials"]))
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("over", [dict(n_samples=1), dict(L=0), dict(N=1), dict(sqp_max_iter=1),
+                                  dict(n_samples=65, L=3)])
+def test_three_state_edge_cases(over):
+    cfg = W.c0_small_nmpc(**dict(dict(n_samples=5, L=5, model_nx=3), **over))
+    phi, stats, ps, _ = gpu_run(cfg)
+    ref = oracle_run(cfg)
+    compare(phi, ps, ref, tag=f"3state edge {over}")
