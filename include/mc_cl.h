@@ -120,7 +120,10 @@ typedef struct {
     int32_t want_grad;        /* PI: keep checkpoints for mc_cl_grad            */
     double noise_scale;       /* 1 stochastic, 0 deterministic run             */
     int32_t ckpt_interval;    /* PI reverse pass: intervals per checkpoint (0 = auto) */
-    int32_t samples_per_wave; /* NMPC lanes used per wavefront (0 = auto)       */
+    /* NMPC samples per wavefront, used exactly; 0 = auto: a cost model's
+     * choice, evened out over the resident wavefronts (the groups made as
+     * small as the same number of rounds allows)                           */
+    int32_t samples_per_wave;
     /* QP solver and Hessian form: 0 primal-dual interior point on the
      * BFGS matrix W (the paper's method family); 1 primal-dual active set on
      * W warm-started from the SQP multipliers, with the interior-point method
@@ -230,7 +233,9 @@ int mc_cl_plan(mc_cl_ctx *c, int32_t *out, int max_classes);
 /* Measured launch-shape tuning (the batching runtime).  For every NMPC
  * horizon class, times the campaign's own samples cut to their first
  * `trial_intervals` closed-loop intervals at each candidate number of
- * samples per wavefront (4, 8, 16, 32, 64) and keeps the fastest; for a
+ * samples per wavefront (at most 4, 8, 16, 32, 64, each evened out over the
+ * resident wavefronts as for samples_per_wave = 0) and keeps the fastest
+ * (spw[] reports the value used); for a
  * campaign with want_grad and PI samples, times the PI forward pass with
  * checkpoints plus the reverse pass at each candidate checkpoint interval
  * C (10, 25, 50, 100, 200; those above the longest sample's L skipped,

@@ -445,6 +445,21 @@ static int choose_spw(int64_t count, int N, int slots_full) {
     return best;
 }
 
+// Samples per wavefront evened out over the wave slots: `spw` is a cap, and
+// the groups are made as small as the same number of rounds (groups per
+// slot, rounded up) allows.  A wavefront's lane phases take the same time
+// however many of its lanes carry samples, and its visits are serial over
+// its samples, so with the rounds unchanged fewer samples per wavefront
+// only shortens each wavefront (c1: 938 groups of 32 on 1,024 slots become
+// 1,000 groups of 30).
+static int balanced_spw(int64_t count, int spw, int slots_full) {
+    const int64_t groups = (count + spw - 1) / spw;
+    const int64_t cap = (int64_t)std::max(slots_full, 1);
+    const int64_t rounds = (groups + cap - 1) / cap;
+    const int64_t b = (count + rounds * cap - 1) / (rounds * cap);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(spw, b));
+}
+
 extern "C" {
 
 uint32_t mc_cl_abi_version(void) { return MC_CL_ABI_VERSION; }
@@ -527,7 +542,10 @@ int mc_cl_create(const mc_cl_params* p, mc_cl_ctx** out) {
         int nmax_in_class = 1;
         for (int64_t q : v) nmax_in_class = std::max(nmax_in_class, Nv[q]);
         const int spw = p->samples_per_wave > 0 ? p->samples_per_wave
-                                                : choose_spw(nc.count, nmax_in_class, nc.slots_full);
+                                                : balanced_spw(nc.count,
+                                                               choose_spw(nc.count, nmax_in_class,
+                                                                          nc.slots_full),
+                                                               nc.slots_full);
         if ((rc = c->alloc(&nc.d_pos, nc.count)) || (rc = plan_class(c, nc, spw))) return fail(rc);
         if (hipMemcpy(nc.d_pos, v.data(), nc.count * 8, hipMemcpyHostToDevice) != hipSuccess)
             return fail(MC_CL_EHIP);
@@ -719,7 +737,8 @@ int mc_cl_tune(mc_cl_ctx* c, void* hip_stream, int32_t trial_intervals, mc_cl_tu
         float best = INFINITY;
         int bspw = nc.spw;
         for (int j = 0; j < MC_CL_TUNE_NSPW && rc == MC_CL_OK; ++j) {
-            if ((rc = plan_class(c, nc, kSpw[j])) != MC_CL_OK) break;
+            const int cand = balanced_spw(nc.count, kSpw[j], nc.slots_full);
+            if ((rc = plan_class(c, nc, cand)) != MC_CL_OK) break;
             float ms = 0.0f;
             rc = timed([&]() -> int {
                 hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, c->d_queue + k, 1, 0);
@@ -734,7 +753,7 @@ int mc_cl_tune(mc_cl_ctx* c, void* hip_stream, int32_t trial_intervals, mc_cl_tu
             r->nmpc_ms[k][j] = ms;
             if (rc == MC_CL_OK && ms < best) {
                 best = ms;
-                bspw = kSpw[j];
+                bspw = cand;
             }
         }
         if (rc == MC_CL_OK) rc = plan_class(c, nc, bspw);

@@ -328,7 +328,8 @@ def test_tune_keeps_results_and_picks_a_candidate():
     camp = binding.Campaign(dict(cfg, want_grad=1))
     res = camp.tune(trial_intervals=3)
     print("tune", res, flush=True)
-    assert res["classes"][0]["spw"] in binding.TUNE_SPW
+    # each candidate is a cap evened out over the resident wavefronts
+    assert 1 <= res["classes"][0]["spw"] <= max(binding.TUNE_SPW)
     assert all(v > 0 for v in res["classes"][0]["trial_ms"].values())
     assert res["ckpt_interval"] in binding.TUNE_CKPT
     assert camp.plan()[0]["spw"] == res["classes"][0]["spw"]
