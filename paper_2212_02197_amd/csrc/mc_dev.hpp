@@ -12,6 +12,20 @@ constexpr double kMlMinPerLs = 60000.0;   // 1 L/s = 60000 mL/min
 constexpr int kSpMax = 8;
 constexpr int kTile = 64;                  // lanes per wavefront (CDNA)
 
+// Lane tiles (the SQP's per-sample vectors of a wavefront's samples): in the
+// block of one vector, element k of the sample on lane l sits at
+//   (k / 16) * 1024 + l * 16 + k % 16,
+// so each lane's sixteen consecutive elements fill one 128-byte cache line.
+// A cooperative visit then reads one sample's vector in 4 lines instead of
+// 64 (the visits' memory traffic was dominated by such column reads), and
+// the one-sample-per-lane phases, which walk k, read sixteen consecutive
+// elements from the same lines.  A lane's pointer into a vector is
+// block + l * kTB; element k is at offset te(k).  NMAX is a multiple of kTB.
+constexpr int kTB = 16;
+__device__ __forceinline__ int te(int k) {
+    return (int)(((unsigned)k / kTB) * (kTB * kTile) + ((unsigned)k % kTB));
+}
+
 // Parameters as the kernels see them (passed by value as a kernel argument).
 struct DevParams {
     double V, k0, EaR, beta, cAin, cBin, cTin;
@@ -398,7 +412,7 @@ __device__ __noinline__ Setup sample_setup(const DevParams& p, int64_t sid) {
 }
 
 // ---------------------------------------------------- single shooting ---
-// Lane-tiled vectors: element k of the lane's sample at t[k * kTile].
+// Lane-tiled vectors: element k of the lane's sample at t[te(k)].
 // Objective of the OCP at u + alpha d (d ignored when use_d is false).
 //
 // With kRec the pass also records, for every control interval k, what the
@@ -425,8 +439,8 @@ __device__ __forceinline__ double ocp_shoot(const DevParams& p, int N, double x0
         double uk = un;
         if (use_d) uk = uk + alpha * dn;
         if (k + 1 < N) {
-            un = u[(k + 1) * kTile];
-            if (use_d) dn = d[(k + 1) * kTile];
+            un = u[te(k + 1)];
+            if (use_d) dn = d[te(k + 1)];
         }
         const double F = uk / kMlMinPerLs;
         double A = 1.0, B = 0.0;
@@ -500,8 +514,8 @@ __device__ __forceinline__ double ocp_shoot3(const DevParams& p, int N, const do
         double uk = un;
         if (use_d) uk = uk + alpha * dn;
         if (k + 1 < N) {
-            un = u[(k + 1) * kTile];
-            if (use_d) dn = d[(k + 1) * kTile];
+            un = u[te(k + 1)];
+            if (use_d) dn = d[te(k + 1)];
         }
         const double F = uk / kMlMinPerLs;
         double A[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
@@ -607,7 +621,7 @@ __device__ __forceinline__ void kkt_add(KktSums& r, double g, double pl, double 
 // from x0 with the inputs u, and the tangents of every u_j, j <= k, are
 // carried through each RK4 step with the stage derivatives (NMAX register
 // slots, unrolled); dphi/du_j accumulates in the lane tile `acc` (element j
-// at acc[j * kTile]).  Returns the sums of the next KKT test with the
+// at acc[te(j)]).  Returns the sums of the next KKT test with the
 // multipliers pil, piu.
 template <int NMAX>
 __device__ __forceinline__ KktSums ocp_grad_fwd(const DevParams& p, int N, double x0, int i0,
@@ -622,11 +636,11 @@ __device__ __forceinline__ KktSums ocp_grad_fwd(const DevParams& p, int N, doubl
 #pragma unroll
     for (int j = 0; j < NMAX; ++j) S[j] = 0.0;
 #pragma unroll 1
-    for (int j = 0; j < N; ++j) acc[j * kTile] = 0.0;
+    for (int j = 0; j < N; ++j) acc[te(j)] = 0.0;
     double x = x0;
 #pragma unroll 1
     for (int k = 0; k < N; ++k) {
-        const double F = u[k * kTile] / kMlMinPerLs;
+        const double F = u[te(k)] / kMlMinPerLs;
 #pragma unroll 1
         for (int c = 0; c < p.Nc; ++c) {
             double a[4], b[4];
@@ -651,15 +665,15 @@ __device__ __forceinline__ KktSums ocp_grad_fwd(const DevParams& p, int N, doubl
         const double dphidx = p.Qz * 2.0 * ez * iV * p.Ts;
 #pragma unroll
         for (int j = 0; j < NMAX; ++j)
-            if (j <= k) acc[j * kTile] += dphidx * S[j];
+            if (j <= k) acc[te(j)] += dphidx * S[j];
     }
     KktSums r{0.0, 0.0, false};
 #pragma unroll 1
     for (int j = 0; j < N; ++j) {
-        const double gj = acc[j * kTile];
-        if (y) y[j * kTile] = gj - g[j * kTile];
-        g[j * kTile] = gj;
-        kkt_add(r, gj, pil[j * kTile], piu[j * kTile]);
+        const double gj = acc[te(j)];
+        if (y) y[te(j)] = gj - g[te(j)];
+        g[te(j)] = gj;
+        kkt_add(r, gj, pil[te(j)], piu[te(j)]);
     }
     return r;
 }

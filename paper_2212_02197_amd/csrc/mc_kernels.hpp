@@ -39,7 +39,7 @@ struct Outs {
 };
 
 // Lane-tiled per-sample vectors of the SQP (element k of lane l's sample at
-// base[(v * NMAX + k) * 64 + l]).
+// base[v * NMAX * 64 + te(k) + l * kTB], the blocked layout of mc_dev.hpp).
 // V_WD: diag(W) and V_V: W d, then W s after the line search (inverse form).
 enum : int { V_U = 0, V_G, V_D, V_PIL, V_PIU, V_NL, V_NU, V_S, V_Y, V_WD, V_V, V_COUNT };
 
@@ -172,12 +172,12 @@ __device__ __forceinline__ VisitOut coop_visit_h(double* TB, double* Ws, lds_dou
     umax = uni_d(umax);
     VisitOut vo{0.0, 0, 0, 0, 0, 0, 0, 0.0};
     const bool in = lane < Ns_;
-    double* const wdp = TB + (V_WD * NMAX + lane) * 64 + s;
+    double* const wdp = TB + V_WD * NMAX * 64 + te(lane) + s * kTB;
     // the sample's vectors (column s of the lane tiles) are loaded while H
     // is being staged
     coop_stage_issue<NMAX>(Ws, Wl, lane);
     const int lt = in ? lane : 0;
-    const double* const tcol = TB + lt * 64 + s;
+    const double* const tcol = TB + te(lt) + s * kTB;
     double wd = tcol[V_WD * NMAX * 64], si = tcol[V_S * NMAX * 64], yi = tcol[V_Y * NMAX * 64];
     double vi = tcol[V_V * NMAX * 64], gi = tcol[V_G * NMAX * 64], ui = tcol[V_U * NMAX * 64];
     double li = tcol[V_PIL * NMAX * 64] - tcol[V_PIU * NMAX * 64];
@@ -227,10 +227,10 @@ __device__ __forceinline__ VisitOut coop_visit_h(double* TB, double* Ws, lds_dou
         if (r.status == 1) vo.ipmcap = 1;
         vo.gd = wave_sum(in ? gi * d : 0.0);
         if (in) {
-            TB[(V_D * NMAX + lane) * 64 + s] = d;
-            TB[(V_NL * NMAX + lane) * 64 + s] = nl;
-            TB[(V_NU * NMAX + lane) * 64 + s] = nu;
-            TB[(V_V * NMAX + lane) * 64 + s] = wdd;
+            TB[V_D * NMAX * 64 + te(lane) + s * kTB] = d;
+            TB[V_NL * NMAX * 64 + te(lane) + s * kTB] = nl;
+            TB[V_NU * NMAX * 64 + te(lane) + s * kTB] = nu;
+            TB[V_V * NMAX * 64 + te(lane) + s * kTB] = wdd;
         }
     }
     __syncthreads();
@@ -258,14 +258,14 @@ __device__ __noinline__ VisitOut coop_visit_w(double* TB, double* Ws, lds_double
     const bool in = lane < Ns_;
     coop_stage<NMAX>(Ws, Wl, lane);
     if (flags & 1) {
-        const double si = in ? TB[(V_S * NMAX + lane) * 64 + s] : 0.0;
-        const double yi = in ? TB[(V_Y * NMAX + lane) * 64 + s] : 0.0;
+        const double si = in ? TB[V_S * NMAX * 64 + te(lane) + s * kTB] : 0.0;
+        const double yi = in ? TB[V_Y * NMAX * 64 + te(lane) + s * kTB] : 0.0;
         if (!coop_bfgs<NMAX>(Wl, Ws, Ns_, lane, si, yi)) vo.skip = 1;
     }
     if (flags & 2) {
-        const double gi = in ? TB[(V_G * NMAX + lane) * 64 + s] : 0.0;
-        const double ui = in ? TB[(V_U * NMAX + lane) * 64 + s] : 0.0;
-        const double li = in ? TB[(V_PIL * NMAX + lane) * 64 + s] - TB[(V_PIU * NMAX + lane) * 64 + s]
+        const double gi = in ? TB[V_G * NMAX * 64 + te(lane) + s * kTB] : 0.0;
+        const double ui = in ? TB[V_U * NMAX * 64 + te(lane) + s * kTB] : 0.0;
+        const double li = in ? TB[V_PIL * NMAX * 64 + te(lane) + s * kTB] - TB[V_PIU * NMAX * 64 + te(lane) + s * kTB]
                              : 0.0;
         double d = 0.0, nl = 0.0, nu = 0.0, Dg = 1.0;
         QPResult r{0, 0};
@@ -293,9 +293,9 @@ __device__ __noinline__ VisitOut coop_visit_w(double* TB, double* Ws, lds_double
         if (r.status == 1) vo.ipmcap = 1;
         vo.gd = wave_sum(in ? gi * d : 0.0);
         if (in) {
-            TB[(V_D * NMAX + lane) * 64 + s] = d;
-            TB[(V_NL * NMAX + lane) * 64 + s] = nl;
-            TB[(V_NU * NMAX + lane) * 64 + s] = nu;
+            TB[V_D * NMAX * 64 + te(lane) + s * kTB] = d;
+            TB[V_NL * NMAX * 64 + te(lane) + s * kTB] = nl;
+            TB[V_NU * NMAX * 64 + te(lane) + s * kTB] = nu;
         }
     }
     __syncthreads();
@@ -315,7 +315,7 @@ __device__ __noinline__ double coop_visit_shift(double* TB, double* Ws, lds_doub
     coop_stage<NMAX>(Ws, Wl, lane);
     double fl = 0.0;
     if (inverse) {
-        const double wlast = TB[(V_WD * NMAX + Ns_ - 1) * 64 + s];
+        const double wlast = TB[V_WD * NMAX * 64 + te(Ns_ - 1) + s * kTB];
         coop_shift_h<NMAX>(Wl, Ws, Ns_, lane, wlast, fl);
     } else {
         coop_shift<NMAX>(Wl, Ws, Ns_, lane);
@@ -324,7 +324,7 @@ __device__ __noinline__ double coop_visit_shift(double* TB, double* Ws, lds_doub
 }
 
 // One backward pass over a lane's sample (lane-offset tiles, element k at
-// [k * 64]): the discrete adjoint of the RK4 shooting over the interval
+// [te(k)]): the discrete adjoint of the RK4 shooting over the interval
 // derivatives ocp_shoot recorded, lambda_k = A_k (lambda_{k+1} + c_k) and
 // g_k = dphi/du_k = B_k (lambda_{k+1} + c_k) backwards from lambda_N = 0,
 // fused with, when kUpdate, the step of the
@@ -352,14 +352,14 @@ __device__ __forceinline__ KktSums adjoint_pass(int N, double alpha, const doubl
             Bv[j] = rr[kTile];
             Cc[j] = rr[2 * kTile];
             if (kUpdate) {
-                G0[j] = G[k * 64];
-                u[j] = U[k * 64];
-                dv[j] = Dv[k * 64];
-                pl[j] = PIL[k * 64];
-                pu[j] = PIU[k * 64];
-                nl[j] = NLv[k * 64];
-                nu[j] = NUv[k * 64];
-                vv[j] = Vv[k * 64];
+                G0[j] = G[te(k)];
+                u[j] = U[te(k)];
+                dv[j] = Dv[te(k)];
+                pl[j] = PIL[te(k)];
+                pu[j] = PIU[te(k)];
+                nl[j] = NLv[te(k)];
+                nu[j] = NUv[te(k)];
+                vv[j] = Vv[te(k)];
             }
         }
 #pragma unroll
@@ -372,16 +372,16 @@ __device__ __forceinline__ KktSums adjoint_pass(int N, double alpha, const doubl
                 double p_l = 0.0, p_u = 0.0;
                 if (kUpdate) {
                     const double un = u[j] + alpha * dv[j];
-                    Sv[k * 64] = un - u[j];
-                    U[k * 64] = un;
+                    Sv[te(k)] = un - u[j];
+                    U[te(k)] = un;
                     p_l = pl[j] + alpha * (nl[j] - pl[j]);
                     p_u = pu[j] + alpha * (nu[j] - pu[j]);
-                    PIL[k * 64] = p_l;
-                    PIU[k * 64] = p_u;
-                    Vv[k * 64] = alpha * vv[j];
-                    Y[k * 64] = gk - G0[j];
+                    PIL[te(k)] = p_l;
+                    PIU[te(k)] = p_u;
+                    Vv[te(k)] = alpha * vv[j];
+                    Y[te(k)] = gk - G0[j];
                 }
-                G[k * 64] = gk;
+                G[te(k)] = gk;
                 kkt_add(r, gk, p_l, p_u);
             }
         }
@@ -410,14 +410,14 @@ __device__ __forceinline__ KktSums adjoint_pass3(int N, double alpha, const doub
 #pragma unroll
             for (int e = 0; e < 13; ++e) R[j][e] = rr[e * kTile];
             if (kUpdate) {
-                G0[j] = G[k * 64];
-                u[j] = U[k * 64];
-                dv[j] = Dv[k * 64];
-                pl[j] = PIL[k * 64];
-                pu[j] = PIU[k * 64];
-                nl[j] = NLv[k * 64];
-                nu[j] = NUv[k * 64];
-                vv[j] = Vv[k * 64];
+                G0[j] = G[te(k)];
+                u[j] = U[te(k)];
+                dv[j] = Dv[te(k)];
+                pl[j] = PIL[te(k)];
+                pu[j] = PIU[te(k)];
+                nl[j] = NLv[te(k)];
+                nu[j] = NUv[te(k)];
+                vv[j] = Vv[te(k)];
             }
         }
 #pragma unroll
@@ -432,16 +432,16 @@ __device__ __forceinline__ KktSums adjoint_pass3(int N, double alpha, const doub
                 double p_l = 0.0, p_u = 0.0;
                 if (kUpdate) {
                     const double un = u[j] + alpha * dv[j];
-                    Sv[k * 64] = un - u[j];
-                    U[k * 64] = un;
+                    Sv[te(k)] = un - u[j];
+                    U[te(k)] = un;
                     p_l = pl[j] + alpha * (nl[j] - pl[j]);
                     p_u = pu[j] + alpha * (nu[j] - pu[j]);
-                    PIL[k * 64] = p_l;
-                    PIU[k * 64] = p_u;
-                    Vv[k * 64] = alpha * vv[j];
-                    Y[k * 64] = gk - G0[j];
+                    PIL[te(k)] = p_l;
+                    PIU[te(k)] = p_u;
+                    Vv[te(k)] = alpha * vv[j];
+                    Y[te(k)] = gk - G0[j];
                 }
-                G[k * 64] = gk;
+                G[te(k)] = gk;
                 kkt_add(r, gk, p_l, p_u);
             }
         }
@@ -480,33 +480,34 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
                           const double (&xhat)[NX], int lane, double* TB, double* XS, double* Wslot,
                           double* Wl, int (&cnt)[C_NCNT], double& qfl, bool pair_ls,
                           bool& shifted) {
-    double* const U = TB + (V_U * NMAX) * 64 + lane;
-    double* const G = TB + (V_G * NMAX) * 64 + lane;
-    double* const Dv = TB + (V_D * NMAX) * 64 + lane;
-    double* const PIL = TB + (V_PIL * NMAX) * 64 + lane;
-    double* const PIU = TB + (V_PIU * NMAX) * 64 + lane;
-    double* const NLv = TB + (V_NL * NMAX) * 64 + lane;
-    double* const NUv = TB + (V_NU * NMAX) * 64 + lane;
-    double* const Sv = TB + (V_S * NMAX) * 64 + lane;
-    double* const Yv = TB + (V_Y * NMAX) * 64 + lane;
-    double* const WDv = TB + (V_WD * NMAX) * 64 + lane;
-    double* const Vv = TB + (V_V * NMAX) * 64 + lane;
+    double* const U = TB + (V_U * NMAX) * 64 + lane * kTB;
+    double* const G = TB + (V_G * NMAX) * 64 + lane * kTB;
+    double* const Dv = TB + (V_D * NMAX) * 64 + lane * kTB;
+    double* const PIL = TB + (V_PIL * NMAX) * 64 + lane * kTB;
+    double* const PIU = TB + (V_PIU * NMAX) * 64 + lane * kTB;
+    double* const NLv = TB + (V_NL * NMAX) * 64 + lane * kTB;
+    double* const NUv = TB + (V_NU * NMAX) * 64 + lane * kTB;
+    double* const Sv = TB + (V_S * NMAX) * 64 + lane * kTB;
+    double* const Yv = TB + (V_Y * NMAX) * 64 + lane * kTB;
+    double* const WDv = TB + (V_WD * NMAX) * 64 + lane * kTB;
+    double* const Vv = TB + (V_V * NMAX) * 64 + lane * kTB;
     double* const Xs = XS + lane;
     static constexpr double smax = 100.0;
     static_assert(GMODE == 1 || NX == 1, "forward sensitivities: one-state model only");
+    static_assert(NMAX % kTB == 0, "lane tiles hold whole blocks");
 
     double f = 0.0;
     if (live) {
         const bool fresh = i == 0 || !p.hess_warm;
         #pragma unroll 4
         for (int k = 0; k < N; ++k) {
-            double v = U[k * 64];
+            double v = U[te(k)];
             if (v < p.umin) v = p.umin;
             if (v > p.umax) v = p.umax;
-            U[k * 64] = v;
-            PIL[k * 64] = 0.0;
-            PIU[k * 64] = 0.0;
-            if (fresh) WDv[k * 64] = 1.0;
+            U[te(k)] = v;
+            PIL[te(k)] = 0.0;
+            PIU[te(k)] = 0.0;
+            if (fresh) WDv[te(k)] = 1.0;
         }
     }
     // W = I for the first OCP (and every OCP without the warm start)
@@ -599,8 +600,8 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
             for (int a = 0; a < NX; ++a) xp[a] = __shfl(xhat[a], src, 64);
             const int isp = __shfl(su.istep, src, 64);
             const double sgp = __shfl(su.sign, src, 64);
-            double* const Up = TB + (V_U * NMAX) * 64 + src;
-            double* const Dp = TB + (V_D * NMAX) * 64 + src;
+            double* const Up = TB + (V_U * NMAX) * 64 + src * kTB;
+            double* const Dp = TB + (V_D * NMAX) * 64 + src * kTB;
             for (;;) {
                 const bool s_on = __shfl(searching ? 1 : 0, src, 64) != 0;
                 if (!__ballot(s_on)) break;
@@ -662,13 +663,13 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
             } else {
                 #pragma unroll 4
                 for (int k = 0; k < N; ++k) {
-                    const double uo = U[k * 64];
-                    const double un = uo + alpha * Dv[k * 64];
-                    Sv[k * 64] = un - uo;
-                    U[k * 64] = un;
-                    PIL[k * 64] = PIL[k * 64] + alpha * (NLv[k * 64] - PIL[k * 64]);
-                    PIU[k * 64] = PIU[k * 64] + alpha * (NUv[k * 64] - PIU[k * 64]);
-                    Vv[k * 64] = alpha * Vv[k * 64];
+                    const double uo = U[te(k)];
+                    const double un = uo + alpha * Dv[te(k)];
+                    Sv[te(k)] = un - uo;
+                    U[te(k)] = un;
+                    PIL[te(k)] = PIL[te(k)] + alpha * (NLv[te(k)] - PIL[te(k)]);
+                    PIU[te(k)] = PIU[te(k)] + alpha * (NUv[te(k)] - PIU[te(k)]);
+                    Vv[te(k)] = alpha * Vv[te(k)];
                 }
                 ks = ocp_grad_fwd<NMAX>(p, N, xhat[0], i, su.istep, su.sign, U, G, Yv, Dv, PIL, PIU);
             }
@@ -688,7 +689,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
     double* const TB = wk.tiles + (int64_t)blockIdx.x * wk.tile_stride;
     double* const XS = wk.xs + (int64_t)blockIdx.x * wk.xs_stride;
     double* const Wslot = wk.W + (int64_t)blockIdx.x * wk.w_stride;
-    double* const U = TB + (V_U * NMAX) * 64 + lane;
+    double* const U = TB + (V_U * NMAX) * 64 + lane * kTB;
     const double sqrtR = sqrt(p.Rmeas);
     const double h = p.Ts / (double)p.Ns;
     const double sqh = sqrt(h);
@@ -734,7 +735,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
         uint64_t hsh = 14695981039346656037ull;
         if (has)
             #pragma unroll 1
-            for (int k = 0; k < N; ++k) U[k * 64] = su.ubar * kMlMinPerLs;
+            for (int k = 0; k < N; ++k) U[te(k)] = su.ubar * kMlMinPerLs;
         const int Lmax = wave_max_i(L);
         for (int i = 0; i <= Lmax; ++i) {
             const bool live = has && i <= L;
@@ -787,16 +788,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
                 uint64_t mask = 0;
                 #pragma unroll 4
                 for (int k = 0; k < N; ++k) {
-                    const double v = U[k * 64];
+                    const double v = U[te(k)];
                     if (v <= p.umin + 1e-6 || v >= p.umax - 1e-6) mask |= (1ull << k);
                 }
                 hsh = fnv1a_step(hsh, (uint32_t)i, mask);
                 const double F = U[0] / kMlMinPerLs;
-                double* const WDv = TB + (V_WD * NMAX) * 64 + lane;
+                double* const WDv = TB + (V_WD * NMAX) * 64 + lane * kTB;
                 #pragma unroll 4
                 for (int k = 0; k + 1 < N; ++k) {
-                    U[k * 64] = U[(k + 1) * 64];
-                    WDv[k * 64] = WDv[(k + 1) * 64];
+                    U[te(k)] = U[te(k + 1)];
+                    WDv[te(k)] = WDv[te(k + 1)];
                 }
                 if (out.tu) out.tu[(int64_t)i * out.S + pos] = F;
                 #pragma unroll 1
