@@ -70,7 +70,10 @@ def compare(phi_g, ps_g, ref, sel=None, tag=""):
 
 
 def test_c0_small_nmpc_full():
-    cfg = W.c0_small_nmpc()
+    # two wavefronts of 32 samples (the automatic plan of so small a campaign
+    # would give each sample a wavefront of its own): cooperative visits over
+    # many samples and the paired line search
+    cfg = W.c0_small_nmpc(samples_per_wave=32)
     phi, stats, ps, _ = gpu_run(cfg)
     ref = oracle_run(cfg)
     compare(phi, ps, ref, tag="c0")
@@ -164,7 +167,7 @@ def compare_conditioned(cfg, phi, ps, ref, tag):
 
 def test_c3_uneven_sampled():
     # uneven batch: N ~ U{10, 25, 50}, L ~ U{100..400}, perturbed kinetics
-    cfg = W.c3_uneven(n_samples=24, sample_id_offset=1000)
+    cfg = W.c3_uneven(n_samples=24, sample_id_offset=1000, samples_per_wave=8)
     phi, stats, ps, _ = gpu_run(cfg)
     ref = oracle_run(cfg)
     for f in ("kind", "N", "L", "n_ocp"):
@@ -377,7 +380,7 @@ def test_cu_limited_stream_matches_full_device():
 def test_three_state_c0_full():
     # 64 NMPC samples, N = 10 (the 16-wide horizon class), perturbed
     # steady-state starts; the model matches the plant apart from the noise
-    cfg = W.c0_small_nmpc(model_nx=3)
+    cfg = W.c0_small_nmpc(model_nx=3, samples_per_wave=16)
     phi, stats, ps, _ = gpu_run(cfg)
     ref = oracle_run(cfg)
     good = compare_conditioned(cfg, phi, ps, ref, "c0-3state")
