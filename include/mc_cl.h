@@ -130,7 +130,9 @@ typedef struct {
      * as fallback when the active set has not settled after 8 factorisations;
      * 2 (default) the same active-set iteration on H = W^-1 kept by the
      * inverse BFGS update, whose QP with |A| active bounds costs one H g
-     * product and an |A| x |A| solve (fallback: interior point on H^-1).
+     * product and an |A| x |A| solve; sets not settled after 8 full updates
+     * continue with least-index single changes (at most 64), and only then
+     * fall back to the interior point on H^-1.
      * All return the QP's unique minimiser; the SQP iterates are the same up
      * to rounding.                                                          */
     int32_t qp_solver;
