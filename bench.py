@@ -103,7 +103,7 @@ def cpu_baseline(cfg, seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; --gpus above 1 is not supported "
+        print("bench.py: measures one GPU; --gpus above 1 is not supported "
               "(samples are independent: a multi-GPU campaign shards sample ids)", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -42,7 +42,7 @@ enum {
     MC_CL_EHIP = -2,         /* HIP runtime error (text kept for strerror)      */
     MC_CL_ENOMEM = -3,       /* device allocation failed                        */
     MC_CL_ESTATE = -4,       /* call out of order (costs before run, ...)       */
-    MC_CL_EUNSUPPORTED = -5  /* valid request this build does not handle        */
+    MC_CL_EUNSUPPORTED = -5  /* valid request the library does not handle      */
 };
 
 /* Per-sample counter rows of mc_cl_outputs.counters ([MC_CL_NCNT][S]).      */
