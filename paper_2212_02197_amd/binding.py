@@ -298,6 +298,7 @@ def _pi_closed_loop_function():
             camp = Campaign(dict(cfg, kP=Kc, kI=Kc / taui, want_grad=1))
             camp.run()
             ctx.camp = camp
+            ctx.theta_device = theta.device
             return camp.phi.clone()
 
         @staticmethod
@@ -306,8 +307,8 @@ def _pi_closed_loop_function():
             _, ps = camp.grad(per_sample=True)
             camp.close()
             ctx.camp = None
-            g = ps @ gout.to(ps.dtype)
-            return g.to(gout.device), None
+            g = ps @ gout.to(device=ps.device, dtype=ps.dtype)
+            return g.to(ctx.theta_device), None
 
     return PIClosedLoop
 

@@ -287,6 +287,11 @@ def test_pi_autograd_function():
     g_ref = ref["dphi"].mean(axis=0)
     np.testing.assert_allclose(g, g_ref, rtol=1e-9)
     assert float(loss) == pytest.approx(ref["phi"].mean(), rel=1e-9)
+    # theta on the host: the gradient comes back on the host
+    th_cpu = theta.detach().cpu().requires_grad_(True)
+    binding.pi_closed_loop(th_cpu, cfg).mean().backward()
+    assert th_cpu.grad.device.type == "cpu"
+    np.testing.assert_allclose(th_cpu.grad.numpy(), g, rtol=1e-12)
     for b in range(2):
         h = 1e-6 * abs(float(theta[b]))
         vals = []
