@@ -170,6 +170,11 @@ struct mc_cl_ctx {
     double* d_gk = nullptr;
     double* d_gsum = nullptr;
     hipEvent_t ev[6] = {};
+    // side streams of the concurrent horizon classes (classes 1 and 2), and
+    // the fork/join events that order them against the caller's stream
+    hipStream_t side[2] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[2] = {};
     hipStream_t last = nullptr;
     bool ran = false;
     bool grad_ran = false;
@@ -217,6 +222,20 @@ struct mc_cl_ctx {
         for (void* v : allocs) (void)hipFree(v);
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
+        for (auto& sd : side)
+            if (sd) (void)hipStreamDestroy(sd);
+        if (fork) (void)hipEventDestroy(fork);
+        for (auto& e : join)
+            if (e) (void)hipEventDestroy(e);
+    }
+    // The side streams and events, created on first use (default priority,
+    // not blocking on the null stream).
+    int ensure_side() {
+        if (fork) return MC_CL_OK;
+        for (auto& sd : side) HIPCHK(hipStreamCreateWithFlags(&sd, hipStreamNonBlocking));
+        for (auto& e : join) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        return MC_CL_OK;
     }
 };
 
@@ -336,13 +355,29 @@ static int launch_step(mc_cl_ctx* c, hipStream_t st, const Outs& out, bool chunk
         hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, c->d_queue, 4, 0);
         HIPCHK(hipGetLastError());
     }
+    // Horizon classes run concurrently (unchunked runs on the whole device):
+    // the waves of one class's launch take the SIMDs that another's tail
+    // leaves idle, as one persistent launch over all classes would.  Their
+    // queues, workspaces and output positions are disjoint.
+    const bool conc = !chunk && c->classes.size() > 1 && c->prm.cu_limit == 0 && c->fork;
+    if (conc) {
+        HIPCHK(hipEventRecord(c->fork, st));
+        for (size_t k = 1; k < c->classes.size(); ++k)
+            HIPCHK(hipStreamWaitEvent(c->side[k - 1], c->fork, 0));
+    }
     for (size_t k = 0; k < c->classes.size(); ++k) {
         const NmpcClass& nc = c->classes[k];
         NmpcWork wk{nc.d_pos, nc.count, nc.spw, nc.groups, c->d_queue + k,
                     chunk ? c->d_ctl + 1 + k : nullptr, nc.d_tiles, nc.d_xs, nc.d_W,
                     nc.tile_stride, nc.xs_stride, nc.w_stride};
         HIPCHK(dispatch_nmpc(nc.nmax, c->prm.grad_mode, c->prm.model_nx, c->dp, wk, out, nc.slots,
-                             st));
+                             conc && k > 0 ? c->side[k - 1] : st));
+    }
+    if (conc) {
+        for (size_t k = 1; k < c->classes.size(); ++k) {
+            HIPCHK(hipEventRecord(c->join[k - 1], c->side[k - 1]));
+            HIPCHK(hipStreamWaitEvent(st, c->join[k - 1], 0));
+        }
     }
     if (ev_mid) HIPCHK(hipEventRecord(ev_mid, st));
     if (c->n_pi) {
@@ -602,6 +637,10 @@ int mc_cl_run(mc_cl_ctx* c, void* hip_stream, const mc_cl_outputs* o) {
         for (int k = 0; k < c->n_chunks; ++k) HIPCHK(hipGraphLaunch(c->gexec, st));
         HIPCHK(hipEventRecord(c->ev[1], st));
     } else {
+        if (c->classes.size() > 1 && c->prm.cu_limit == 0) {
+            const int rc = c->ensure_side();
+            if (rc != MC_CL_OK) return rc;
+        }
         HIPCHK(hipEventRecord(c->ev[0], st));
         const int rc = launch_step(c, st, out, false, c->ev[1]);
         if (rc != MC_CL_OK) return rc;
