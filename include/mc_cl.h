@@ -121,8 +121,9 @@ typedef struct {
     double noise_scale;       /* 1 stochastic, 0 deterministic run             */
     int32_t ckpt_interval;    /* PI reverse pass: intervals per checkpoint (0 = auto) */
     /* NMPC samples per wavefront, used exactly; 0 = auto: a cost model's
-     * choice, evened out over the resident wavefronts when the groups fit
-     * in one round (then made as small as the resident wavefronts allow)   */
+     * choice, evened out over the resident wavefronts (made as small as the
+     * same number of rounds allows; by at most an eighth when the groups
+     * take several rounds)                                                  */
     int32_t samples_per_wave;
     /* QP solver and Hessian form: 0 primal-dual interior point on the
      * BFGS matrix W (the paper's method family); 1 primal-dual active set on

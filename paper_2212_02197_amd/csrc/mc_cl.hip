@@ -480,21 +480,24 @@ static int choose_spw(int64_t count, int N, int slots_full) {
     return best;
 }
 
-// Samples per wavefront evened out over the wave slots when the groups fit
-// in one round (at most one group per resident wavefront): `spw` is a cap,
-// and the groups are made as small as the slots allow.  A wavefront's lane
-// phases take the same time however many of its lanes carry samples, and
-// its visits are serial over its samples, so fewer samples per wavefront
-// only shortens each wavefront (c1: 938 groups of 32 on 1,024 slots become
-// 1,000 groups of 30).  With several rounds the queue balances the
-// wavefronts already, and smaller groups would only add lock-step rounds
-// (each group runs an interval's SQP until its slowest sample is done).
+// Samples per wavefront evened out over the wave slots: `spw` is a cap, and
+// the groups are made as small as the same number of rounds (groups per
+// resident wavefront, rounded up) allows.  A wavefront's lane phases take
+// the same time however many of its lanes carry samples, and its visits are
+// serial over its samples, so fewer samples per wavefront only shortens
+// each wavefront (c1: 938 groups of 32 on 1,024 slots become 1,000 groups
+// of 30; c4: 7,813 groups of 64 in 8 rounds become 8,065 of 62).  With
+// several rounds the groups are shrunk by at most an eighth: much smaller
+// groups add lock-step rounds (each group runs an interval's SQP until its
+// slowest sample is done), which cost more than the filled last round saves
+// (c3's N = 50 class, 32 to 17 per group: 2 % slower).
 static int balanced_spw(int64_t count, int spw, int slots_full) {
     const int64_t groups = (count + spw - 1) / spw;
     const int64_t cap = (int64_t)std::max(slots_full, 1);
-    if (groups > cap) return spw;
-    const int64_t b = (count + cap - 1) / cap;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(spw, b));
+    const int64_t rounds = (groups + cap - 1) / cap;
+    const int64_t b = std::max<int64_t>(1, (count + rounds * cap - 1) / (rounds * cap));
+    if (rounds > 1 && 8 * b < 7 * (int64_t)spw) return spw;
+    return (int)std::min<int64_t>(spw, b);
 }
 
 extern "C" {
