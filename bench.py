@@ -167,6 +167,22 @@ def main():
                         traffic=measured_traffic()
                         if args.config == "c1" and not args.samples and args.model_nx == 1 else None)
     camp_flops = stats["flops_algorithmic"]
+    pi_grad = None
+    if cfg.get("want_grad") and n_pi:
+        # the PI reverse pass (checkpointed adjoint through the closed loop)
+        # after the timed forward step: d mean Phi / d(Kc, tau_i)
+        torch.cuda.synchronize()
+        tg0 = time.perf_counter()
+        g, _ = camp.grad()
+        torch.cuda.synchronize()
+        tg1 = time.perf_counter()
+        ms_grad = camp.kernel_ms()[3]
+        pi_grad = dict(samples=n_pi, forward_ms=round(ms_kernels[1], 3),
+                       reverse_ms=round(ms_grad, 3), wall_ms=round((tg1 - tg0) * 1000.0, 3),
+                       samples_per_s=round(n_pi / ((ms_kernels[1] + ms_grad) / 1000.0), 3),
+                       dmeanphi_dKc=g[0], dmeanphi_dtaui=g[1],
+                       ckpt_interval=(tuning or {}).get("ckpt_interval") or cfg.get("ckpt_interval"))
+        log(f"PI gradient: forward {ms_kernels[1]:.1f} ms, reverse {ms_grad:.1f} ms")
     camp.close()
 
     plain = None
@@ -180,7 +196,7 @@ def main():
     out = {
         "metric": "NMPC CSTR closed-loop sims/sec on 1 GPU; % FP64 peak; adjoint vs plain SQP",
         "value": round(value, 3),
-        "unit": "NMPC closed-loop sims/s",
+        "unit": "NMPC closed-loop sims/s" if n_nmpc else "PI closed-loop sims/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -203,6 +219,7 @@ def main():
         "launch_plan": plan,
         "launch_tuning": tuning,
         "cu_scaling": scaling,
+        "pi_gradient": pi_grad,
         "adjoint_vs_plain": plain,
         "algorithmic_gflop_per_step": round(camp_flops / 1e9, 3),
     }
