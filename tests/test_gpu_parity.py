@@ -330,6 +330,35 @@ def test_chunked_graph_run_matches_single_launch():
     compare(phi1, ps1, ref, sel=ids, tag="c4 chunked")
 
 
+def test_concurrent_horizon_classes_match_sequential_launches():
+    # three horizon classes (N 10 / 25 / 50) with ragged lengths: an
+    # unchunked run on the whole device launches them on concurrent streams;
+    # a positive cu_limit (here all compute units) launches them one after
+    # another on the caller's stream.  Bitwise the same results.
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    cfg = W.c3_uneven(n_samples=90, sample_id_offset=7000, L_lo=15, L_hi=40, samples_per_wave=8)
+    phi_c, _, ps_c, _ = gpu_run(cfg)
+    phi_s, _, ps_s, _ = gpu_run(dict(cfg, cu_limit=n_cu))
+    assert set(ps_c["N"].tolist()) == {10, 25, 50}
+    np.testing.assert_array_equal(phi_c, phi_s)
+    np.testing.assert_array_equal(ps_c["ashash"], ps_s["ashash"])
+    for f in binding.CNT_NAMES:
+        np.testing.assert_array_equal(ps_c[f], ps_s[f], err_msg=f)
+
+
+def test_three_state_chunked_graph_run_matches_single_launch():
+    cfg = W.c0_small_nmpc(n_samples=96, L=10, model_nx=3, samples_per_wave=16)
+    phi1, _, ps1, _ = gpu_run(cfg)
+    camp = binding.Campaign(dict(cfg, chunk_samples=40))
+    for rep in range(2):
+        camp.run()
+        phi, _ = camp.costs()
+        ps = camp.per_sample()
+        np.testing.assert_array_equal(phi, phi1)
+        np.testing.assert_array_equal(ps["sqp_iter"], ps1["sqp_iter"])
+    camp.close()
+
+
 def test_tune_keeps_results_and_picks_a_candidate():
     cfg = W.c0_small_nmpc(n_samples=300, L=10, kind_split=200, noise_mod=200)
     phi0, _, ps0, _ = gpu_run(cfg)
