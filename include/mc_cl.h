@@ -170,7 +170,8 @@ typedef struct {
                                  a bound at the implemented solution           */
     double *traj_z;           /* [L+1][S] output z = c_T (K); needs uniform L  */
     double *traj_u;           /* [L][S] implemented flow (L/s)                 */
-    double *traj_xhat;        /* [L][S] filtered estimate x-hat_{i|i}          */
+    double *traj_xhat;        /* [L][S] filtered estimate x-hat_{i|i} (its n_T
+                                 entry with the three-state model)             */
 } mc_cl_outputs;
 
 /* Campaign statistics (per controller: index 0 NMPC, 1 PI).                 */
@@ -197,8 +198,12 @@ int mc_cl_create(const mc_cl_params *p, mc_cl_ctx **out);
 
 /* Run the campaign asynchronously on hip_stream (a hipStream_t; NULL = the
  * null stream): every sample's closed loop, then the Phi statistics.  Results
- * stay in the context; `o` (may be NULL) names extra device outputs.
- * ESTATE if trajectories are requested with per-sample L.                   */
+ * stay in the context; `o` (may be NULL) names extra device outputs.  With
+ * several horizon classes, no chunking and no cu_limit, the classes' kernels
+ * run concurrently on two library-owned streams forked from hip_stream and
+ * joined back into it by events (same results as one after another).
+ * ESTATE if trajectories are requested with per-sample L; EUNSUPPORTED if
+ * trajectories are requested of a chunked run.                              */
 int mc_cl_run(mc_cl_ctx *c, void *hip_stream, const mc_cl_outputs *o);
 
 /* Wait for the last run, then copy Phi ([S], host, may be NULL) and the
@@ -225,7 +230,8 @@ uint32_t mc_cl_abi_version(void);
 
 /* Diagnostics.
  * mc_cl_kernel_ms: device time (ms, HIP events on the run's stream) of the
- * last run's NMPC kernels [0], PI kernel [1], statistics [2] and of the last
+ * last run's NMPC kernels (all classes, fork to join) [0], PI kernel [1],
+ * statistics [2] and of the last
  * mc_cl_grad reverse pass [3]; waits for the run.  ESTATE before a run.
  * mc_cl_plan: launch plan of the NMPC horizon classes, 5 ints per class
  * {NMAX, samples, samples per wavefront, work groups, resident wavefronts};
