@@ -168,9 +168,13 @@ typedef struct {
     uint64_t *ashash;         /* [S] FNV-1a-64 over (i, active-set bitmask) of
                                  every OCP; bit k set if u_k is within 1e-6 of
                                  a bound at the implemented solution           */
-    double *traj_z;           /* [L+1][S] output z = c_T (K); needs uniform L  */
-    double *traj_u;           /* [L][S] implemented flow (L/s)                 */
-    double *traj_xhat;        /* [L][S] filtered estimate x-hat_{i|i} (its n_T
+    /* Trajectories, row i = interval i, with T = L_hi if L_lo < L_hi (per-
+     * sample lengths) else L: every sample's own length is at most T.  Row i
+     * of a sample's column is written for i <= its L (z) or i < its L (u,
+     * x-hat); later rows of that column are left as they were.              */
+    double *traj_z;           /* [T+1][S] output z = c_T (K)                   */
+    double *traj_u;           /* [T][S] implemented flow (L/s)                 */
+    double *traj_xhat;        /* [T][S] filtered estimate x-hat_{i|i} (its n_T
                                  entry with the three-state model)             */
 } mc_cl_outputs;
 
@@ -202,8 +206,7 @@ int mc_cl_create(const mc_cl_params *p, mc_cl_ctx **out);
  * several horizon classes, no chunking and no cu_limit, the classes' kernels
  * run concurrently on two library-owned streams forked from hip_stream and
  * joined back into it by events (same results as one after another).
- * ESTATE if trajectories are requested with per-sample L; EUNSUPPORTED if
- * trajectories are requested of a chunked run.                              */
+ * EUNSUPPORTED if trajectories are requested of a chunked run.             */
 int mc_cl_run(mc_cl_ctx *c, void *hip_stream, const mc_cl_outputs *o);
 
 /* Wait for the last run, then copy Phi ([S], host, may be NULL) and the
@@ -233,6 +236,8 @@ uint32_t mc_cl_abi_version(void);
  * last run's NMPC kernels (all classes, fork to join) [0], PI kernel [1],
  * statistics [2] and of the last
  * mc_cl_grad reverse pass [3]; waits for the run.  ESTATE before a run.
+ * For a chunked run (chunk_samples > 0) [0] spans every graph replay, NMPC
+ * and PI kernels together, and [1] is -1.                                   
  * mc_cl_plan: launch plan of the NMPC horizon classes, 5 ints per class
  * {NMAX, samples, samples per wavefront, work groups, resident wavefronts};
  * returns the number of classes written (<= max_classes).                   */

@@ -104,6 +104,8 @@ def lib():
             "oc_bfgs_update": (C.c_int, [i32, pd, pd, pd]),
             "oc_sqp": (C.c_int, [P(Params), i32, pd, pd, pd, pd, pd, pd, i32, P(SampleOut)]),
             "oc_run_sample": (None, [P(Params), i64, P(SampleOut), pd, pd, pd]),
+            "oc_run_sample_ext": (None, [P(Params), i64, P(SampleOut), pd, pd, pd, pd]),
+            "oc_scenario": (None, [P(Params), i64, P(i32), pd]),
             "oc_run": (None, [P(Params), P(i64), i64, i32, P(SampleOut)]),
             "oc_stats": (None, [pd, i64, pd, pd, P(i64)]),
         }
@@ -312,20 +314,31 @@ def sqp(cfg, x0, zbar, u0):
 
 
 def run_sample(cfg, sid, traj=False):
-    """One closed-loop sample; returns the result dict (+ trajectories)."""
+    """One closed-loop sample; returns the result dict (+ trajectories:
+    z, u, x-hat and, for PI samples, the integral state I-hat after each
+    interval's update)."""
     p = params(cfg)
     o = SampleOut()
     Lmax = max(cfg["L"], cfg["L_hi"]) + 1
-    tz, tu, tx = np.zeros(Lmax), np.zeros(Lmax), np.zeros(Lmax)
+    tz, tu, tx, ti = np.zeros(Lmax), np.zeros(Lmax), np.zeros(Lmax), np.zeros(Lmax)
     if traj:
-        lib().oc_run_sample(C.byref(p), sid, C.byref(o), _dp(tz), _dp(tu), _dp(tx))
+        lib().oc_run_sample_ext(C.byref(p), sid, C.byref(o), _dp(tz), _dp(tu), _dp(tx), _dp(ti))
     else:
         lib().oc_run_sample(C.byref(p), sid, C.byref(o), None, None, None)
     res = _out_dict(o)
     if traj:
         L = o.L
-        res["z"], res["u"], res["xhat"] = tz[:L + 1], tu[:L], tx[:L]
+        res["z"], res["u"], res["xhat"], res["Ihat"] = tz[:L + 1], tu[:L], tx[:L], ti[:L]
     return res
+
+
+def scenario(cfg, sid):
+    """Per-sample scenario draws: dict(kind, N, L, istep, sign, k0, EaR)."""
+    p = params(cfg)
+    iv = (C.c_int32 * 4)()
+    dv = np.zeros(3)
+    lib().oc_scenario(C.byref(p), sid, iv, _dp(dv))
+    return dict(kind=iv[0], N=iv[1], L=iv[2], istep=iv[3], sign=dv[0], k0=dv[1], EaR=dv[2])
 
 
 def _out_dict(o):

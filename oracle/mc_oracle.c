@@ -977,8 +977,27 @@ static uint64_t fnv1a_bytes(uint64_t h, const unsigned char *b, int n)
     return h;
 }
 
+void oc_scenario(const oc_params *p, int64_t sample_id, int32_t iv[4], double dv[3])
+{
+    oc_setup su;
+    sample_setup(p, sample_id, &su);
+    iv[0] = su.kind;
+    iv[1] = su.N;
+    iv[2] = su.L;
+    iv[3] = su.istep;
+    dv[0] = su.sign;
+    dv[1] = su.k0;
+    dv[2] = su.EaR;
+}
+
 void oc_run_sample(const oc_params *p, int64_t sample_id, oc_sample_out *out,
                    double *traj_z, double *traj_u, double *traj_xhat)
+{
+    oc_run_sample_ext(p, sample_id, out, traj_z, traj_u, traj_xhat, NULL);
+}
+
+void oc_run_sample_ext(const oc_params *p, int64_t sample_id, oc_sample_out *out,
+                       double *traj_z, double *traj_u, double *traj_xhat, double *traj_I)
 {
     oc_setup su;
     double n[3], xhat, P, Fprev, Ihat = 0.0, phiacc = 0.0;
@@ -1099,6 +1118,7 @@ void oc_run_sample(const oc_params *p, int64_t sample_id, oc_sample_out *out,
                 }
             }
             Ihat = Ik + p->Ts * p->kaw * (uh - uk);
+            if (traj_I) traj_I[i] = Ihat;
             F = uk;
         }
         if (traj_u) traj_u[i] = F;

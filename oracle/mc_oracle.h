@@ -114,6 +114,13 @@ int  oc_sqp(const oc_params *p, int32_t N, const double *x0, const double *zbar,
             double *pil, double *piu, double *W, int32_t reset_W, oc_sample_out *cnt);
 void oc_run_sample(const oc_params *p, int64_t sample_id, oc_sample_out *out,
                    double *traj_z, double *traj_u, double *traj_xhat);
+/* As oc_run_sample, also recording the PI integral state after interval i's
+ * update (traj_I[i], PI samples; may be NULL).                              */
+void oc_run_sample_ext(const oc_params *p, int64_t sample_id, oc_sample_out *out,
+                       double *traj_z, double *traj_u, double *traj_xhat, double *traj_I);
+/* The per-sample scenario draws: iv = {kind, N, L, step interval},
+ * dv = {step sign, plant k0, plant Ea/R}.                                   */
+void oc_scenario(const oc_params *p, int64_t sample_id, int32_t iv[4], double dv[3]);
 void oc_run(const oc_params *p, const int64_t *ids, int64_t n, int32_t nthreads,
             oc_sample_out *out);
 void oc_stats(const double *phi, int64_t n, double *mean, double *var,

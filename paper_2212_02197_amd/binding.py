@@ -204,7 +204,9 @@ class Campaign:
         o = Outputs(self.phi.data_ptr(), self.counters.data_ptr(), self.ashash.data_ptr(),
                     None, None, None)
         if trajectories:
-            L = int(self.cfg["L"])
+            # rows for the longest possible sample (mc_cl_outputs: T)
+            c = self.cfg
+            L = int(c["L_hi"] if c["L_lo"] < c["L_hi"] else c["L"])
             dev = self.phi.device
             self.traj = dict(z=torch.empty((L + 1, self.S), dtype=torch.float64, device=dev),
                              u=torch.empty((L, self.S), dtype=torch.float64, device=dev),

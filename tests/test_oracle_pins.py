@@ -508,3 +508,97 @@ def test_stats_against_exact_sums_and_numpy_histogram(oracle):
     assert hist[0] == np.sum(phi <= 1e-4 * (1 - 1e-16)) or hist[0] == np.sum(lg < -4) + 1
     assert hist[201] == np.sum(lg >= 4)
     assert hist.sum() == len(phi)
+
+
+# ------------------------------------------------------------ PI anti-windup ---
+@pytest.mark.parametrize("z_hi", [360.0, 274.0])
+def test_pi_antiwindup_fixed_point_under_saturation(oracle, z_hi):
+    # eq. (PI): I+ = I + Ts kI e + Ts kaw (u-hat - u), u = clip(u-hat),
+    # u-hat = u-bar + kP e + I + Ts kI e.  A setpoint the plant cannot reach
+    # holds the input at one bound: 360 K lies above the adiabatic limit
+    # c_T,in + beta min(c_A,in, c_B,in / 2) = 353.92 K (u at its lower
+    # bound), 274 K below the temperature at the largest flow (upper bound).
+    # With e constant the recursion contracts by (1 + Ts kaw) = 0.9 per
+    # interval to its fixed point
+    #   I* = u_sat - u-bar - kP e - Ts kI e - kI e / kaw,
+    # which a sign slip in kaw (growth by 1.1), an anti-windup term taken
+    # from u-hat before the clip (I grows without bound) or a clip of the
+    # wrong bound would all miss.
+    cfg = W.c1_paper_scale(kind_split=-1, default_kind=1, noise_scale=0.0, L=600,
+                           sp_i=(0, 100), sp_z=(320.0, z_hi))
+    r = oracle.run_sample(cfg, 0, traj=True)
+    z, u, I = r["z"], r["u"], r["Ihat"]
+    ubar, _ = oracle.steady_state(cfg, 320.0)
+    usat = cfg["pi_umin"] if z_hi > 320.0 else cfg["pi_umax"]
+    for i in (450, 520, 599):
+        assert u[i] == usat
+        e = z_hi - z[i]
+        Istar = (usat - ubar - cfg["kP"] * e - cfg["Ts"] * cfg["kI"] * e
+                 - cfg["kI"] * e / cfg["kaw"])
+        assert I[i] == pytest.approx(Istar, rel=1e-12, abs=1e-18)
+    if z_hi > 320.0:
+        # the plant settles at the adiabatic limit once the flow is off
+        Tmax = cfg["cTin"] + cfg["beta"] * min(cfg["cAin"], cfg["cBin"] / 2)
+        assert z[599] == pytest.approx(Tmax, abs=1e-9)
+
+
+# ------------------------------------------------------------ scenario draws ---
+def _scenarios(oracle, cfg, ids):
+    rows = [oracle.scenario(cfg, int(s)) for s in ids]
+    return {k: np.array([r[k] for r in rows]) for k in rows[0]}
+
+
+def test_scenario_draws_horizon_and_length_are_uniform_and_independent(oracle):
+    # c3 recipe: N ~ U{10, 25, 50}, L ~ U{100..400}, drawn independently
+    cfg = W.c3_uneven()
+    ids = np.arange(12000)
+    sc = _scenarios(oracle, cfg, ids)
+    cN = np.array([(sc["N"] == v).sum() for v in (10, 25, 50)])
+    assert cN.sum() == len(ids)
+    assert stats.chisquare(cN).pvalue > 1e-3
+    assert sc["L"].min() >= 100 and sc["L"].max() <= 400
+    cL = np.bincount(sc["L"] - 100, minlength=301)
+    assert len(cL) == 301 and stats.chisquare(cL).pvalue > 1e-3
+    # both ends of the range are reachable (no off-by-one at 400)
+    assert cL[0] > 0 and cL[300] > 0
+    # independence of N and L: contingency table of N against L tercile
+    terc = np.digitize(sc["L"], [200, 300])
+    table = np.array([[((sc["N"] == v) & (terc == t)).sum() for t in range(3)]
+                      for v in (10, 25, 50)])
+    assert stats.chi2_contingency(table).pvalue > 1e-3
+
+
+def test_scenario_draws_step_time_and_sign(oracle):
+    # c4 recipe: setpoint step at U{50..250}, sign a fair coin
+    cfg = W.c4_mixed()
+    ids = np.arange(12000)
+    sc = _scenarios(oracle, cfg, ids)
+    assert sc["istep"].min() >= 50 and sc["istep"].max() <= 250
+    c = np.bincount(sc["istep"] - 50, minlength=201)
+    assert len(c) == 201 and stats.chisquare(c).pvalue > 1e-3
+    assert set(np.unique(sc["sign"]).tolist()) == {-1.0, 1.0}
+    assert stats.binomtest(int((sc["sign"] > 0).sum()), len(ids), 0.5).pvalue > 1e-3
+    # NMPC / PI pairs share noise ids, so sample s and s + 500,000 share
+    # their scenario
+    pair = _scenarios(oracle, cfg, ids + 500000)
+    np.testing.assert_array_equal(pair["istep"], sc["istep"])
+    np.testing.assert_array_equal(pair["sign"], sc["sign"])
+    assert pair["kind"].tolist() == [1] * len(ids) and sc["kind"].tolist() == [0] * len(ids)
+
+
+def test_scenario_draws_lognormal_kinetics(oracle):
+    # c3 plant kinetics: k0 and Ea/R each times exp(0.05 xi), xi ~ N(0, 1)
+    # independent; the model keeps the nominal values
+    cfg = W.c3_uneven()
+    ids = np.arange(12000)
+    sc = _scenarios(oracle, cfg, ids)
+    a = np.log(sc["k0"] / cfg["k0"]) / cfg["kin_lognorm_sigma"]
+    b = np.log(sc["EaR"] / cfg["EaR"]) / cfg["kin_lognorm_sigma"]
+    for x in (a, b):
+        assert stats.kstest(x, "norm").pvalue > 1e-3
+        assert abs(x.mean()) < 5 / math.sqrt(len(x))
+        assert abs(x.std(ddof=1) - 1.0) < 5 / math.sqrt(2 * len(x))
+    assert abs(np.corrcoef(a, b)[0, 1]) < 5 / math.sqrt(len(a))
+    # without the perturbation the plant keeps the nominal kinetics
+    nom = oracle.scenario(W.c0_small_nmpc(), 7)
+    assert nom["k0"] == cfg["k0"] and nom["EaR"] == cfg["EaR"]
