@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define MC_CL_ABI_VERSION 4u
+#define MC_CL_ABI_VERSION 5u
 #define MC_CL_SPMAX 8        /* setpoint schedule levels                        */
 #define MC_CL_NMAX 64        /* largest NMPC horizon                            */
 #define MC_CL_NHIST 202      /* histogram: underflow, 200 bins, overflow        */
@@ -157,6 +157,21 @@ typedef struct {
      * state at zbar(0) (x0_mode 1).  Other values: EINVAL; 3 with
      * grad_mode 0: EUNSUPPORTED (forward sensitivities are one-state only). */
     int32_t model_nx;
+    /* Optional per-sample arrays, host memory of n_samples entries each,
+     * copied by mc_cl_create (NULL: the rules above).  Column s of every
+     * output is the sample these arrays give at index s.
+     *   sample_ids: global sample id (0 .. 2^32 - 2) that keys the sample's
+     *     noise and scenario draws and the kind_split test; default
+     *     sample_id_offset + s.  Ids may repeat or come in any order
+     *     (strided subsets of a campaign).
+     *   kind: 0 NMPC, 1 PI, in place of kind_split / default_kind.
+     *   horizon: N (1..64), in place of N and horizon_choices.
+     *   lengths: L (0 .. 2^24), in place of L and L_lo..L_hi.
+     * EINVAL for a value outside its range.                                 */
+    const int64_t *sample_ids;
+    const uint8_t *kind;
+    const int32_t *horizon;
+    const int32_t *lengths;
 } mc_cl_params;
 
 /* Optional outputs of mc_cl_run; every pointer may be NULL.  All are device
@@ -168,8 +183,9 @@ typedef struct {
     uint64_t *ashash;         /* [S] FNV-1a-64 over (i, active-set bitmask) of
                                  every OCP; bit k set if u_k is within 1e-6 of
                                  a bound at the implemented solution           */
-    /* Trajectories, row i = interval i, with T = L_hi if L_lo < L_hi (per-
-     * sample lengths) else L: every sample's own length is at most T.  Row i
+    /* Trajectories, row i = interval i, with T = the largest entry of
+     * lengths[] when given, else L_hi if L_lo < L_hi (drawn lengths), else L:
+     * every sample's own length is at most T.  Row i
      * of a sample's column is written for i <= its L (z) or i < its L (u,
      * x-hat); later rows of that column are left as they were.              */
     double *traj_z;           /* [T+1][S] output z = c_T (K)                   */

@@ -16,6 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = os.path.join(_HERE, "libmc_oracle.so")
 _SRC = os.path.join(_HERE, "mc_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "mc_oracle_ms.c")]
 SPMAX = 8
 NMAX = 64
 
@@ -23,10 +24,10 @@ NMAX = 64
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc -O2 (no fast-math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
-            os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "mc_oracle.h"))):
+            [os.path.getmtime(f) for f in _SRCS] + [os.path.getmtime(os.path.join(_HERE, "mc_oracle.h"))]):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm", "-lpthread"])
+                               "-o", tmp, *_SRCS, "-lm", "-lpthread"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -55,6 +56,7 @@ class Params(C.Structure):
         ("L_lo", C.c_int32), ("L_hi", C.c_int32),
         ("kin_lognorm_sigma", C.c_double),
         ("hess_warm", C.c_int32), ("model_nx", C.c_int32), ("noise_scale", C.c_double),
+        ("nlp_form", C.c_int32),
     ]
 
 
@@ -104,10 +106,14 @@ def lib():
             "oc_bfgs_update": (C.c_int, [i32, pd, pd, pd]),
             "oc_sqp": (C.c_int, [P(Params), i32, pd, pd, pd, pd, pd, pd, i32, P(SampleOut)]),
             "oc_run_sample": (None, [P(Params), i64, P(SampleOut), pd, pd, pd]),
-            "oc_run_sample_ext": (None, [P(Params), i64, P(SampleOut), pd, pd, pd, pd]),
+            "oc_run_sample_ext": (None, [P(Params), i64, P(i32), P(SampleOut), pd, pd, pd, pd]),
+            "oc_run_ov": (None, [P(Params), P(i64), P(i32), i64, i32, P(SampleOut)]),
             "oc_scenario": (None, [P(Params), i64, P(i32), pd]),
             "oc_run": (None, [P(Params), P(i64), i64, i32, P(SampleOut)]),
             "oc_stats": (None, [pd, i64, pd, pd, P(i64)]),
+            "oc_ms_interval": (None, [P(Params), d, d, pd]),
+            "oc_ms_qp": (C.c_int, [P(Params), i32, pd, pd, pd, pd, pd, pd, pd, pd, pd, pd, P(i32)]),
+            "oc_ms_sqp": (C.c_int, [P(Params), i32, d, pd, pd, pd, P(SampleOut)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -129,6 +135,8 @@ def params(cfg: dict) -> Params:
         setattr(p, key, cfg[key])
     p.model_nx = cfg.get("model_nx", 1)
     assert p.model_nx in (1, 3)
+    p.nlp_form = cfg.get("nlp_form", 0)
+    assert p.nlp_form in (0, 1) and (p.nlp_form == 0 or p.model_nx == 1)
     for a in range(3):
         p.sigma[a] = cfg["sigma"][a]
     sp_i, sp_z = cfg["sp_i"], cfg["sp_z"]
@@ -322,7 +330,8 @@ def run_sample(cfg, sid, traj=False):
     Lmax = max(cfg["L"], cfg["L_hi"]) + 1
     tz, tu, tx, ti = np.zeros(Lmax), np.zeros(Lmax), np.zeros(Lmax), np.zeros(Lmax)
     if traj:
-        lib().oc_run_sample_ext(C.byref(p), sid, C.byref(o), _dp(tz), _dp(tu), _dp(tx), _dp(ti))
+        lib().oc_run_sample_ext(C.byref(p), sid, None, C.byref(o), _dp(tz), _dp(tu), _dp(tx),
+                                _dp(ti))
     else:
         lib().oc_run_sample(C.byref(p), sid, C.byref(o), None, None, None)
     res = _out_dict(o)
@@ -347,9 +356,10 @@ def _out_dict(o):
     return r
 
 
-def run(cfg, ids=None, nthreads=None):
-    """Closed loop for the given sample ids on a thread pool.  Returns a dict
-    of numpy arrays, one entry per field of SampleOut."""
+def run(cfg, ids=None, nthreads=None, kind=None, horizon=None, lengths=None):
+    """Closed loop for the given sample ids on a thread pool.  kind, horizon
+    and lengths (optional, aligned with ids) replace the per-sample rules.
+    Returns a dict of numpy arrays, one entry per field of SampleOut."""
     if ids is None:
         ids = np.arange(cfg["n_samples"], dtype=np.int64)
     ids = np.ascontiguousarray(ids, dtype=np.int64)
@@ -358,7 +368,15 @@ def run(cfg, ids=None, nthreads=None):
         nthreads = len(os.sched_getaffinity(0))
     p = params(cfg)
     outs = (SampleOut * n)()
-    lib().oc_run(C.byref(p), ids.ctypes.data_as(C.POINTER(C.c_int64)), n, nthreads, outs)
+    if kind is None and horizon is None and lengths is None:
+        lib().oc_run(C.byref(p), ids.ctypes.data_as(C.POINTER(C.c_int64)), n, nthreads, outs)
+    else:
+        ov = np.full((3, n), -1, dtype=np.int32)
+        for row, a in enumerate((kind, horizon, lengths)):
+            if a is not None:
+                ov[row] = np.asarray(a, dtype=np.int32)
+        lib().oc_run_ov(C.byref(p), ids.ctypes.data_as(C.POINTER(C.c_int64)),
+                        ov.ctypes.data_as(C.POINTER(C.c_int32)), n, nthreads, outs)
     arr = np.frombuffer(outs, dtype=np.dtype({
         "names": OUT_FIELDS,
         "formats": ["f8", ("f8", 2), "u8"] + ["i4"] * 14,
@@ -376,3 +394,33 @@ def stats(phi):
     lib().oc_stats(_dp(phi), len(phi), C.byref(m), C.byref(v),
                    hist.ctypes.data_as(C.POINTER(C.c_int64)))
     return m.value, v.value, hist
+
+
+def ms_interval(cfg, x, u):
+    """One sampling interval of the one-state model: (F, dF/dx, dF/du)."""
+    o = np.zeros(3)
+    lib().oc_ms_interval(C.byref(params(cfg)), x, u, _dp(o))
+    return tuple(o)
+
+
+def ms_qp(cfg, W, gf, A, B, c, u):
+    """The structured QP of the multiple-shooting SQP (condensed, dense):
+    returns (status, dxi, mu, nu_l, nu_u, iterations)."""
+    N = len(u)
+    arr = [np.ascontiguousarray(v, dtype=np.float64) for v in (W, gf, A, B, c, u)]
+    dxi, mu, nl, nu = np.zeros(2 * N), np.zeros(N), np.zeros(N), np.zeros(N)
+    it = C.c_int32()
+    st = lib().oc_ms_qp(C.byref(params(cfg)), N, *[_dp(a) for a in arr], _dp(dxi), _dp(mu),
+                        _dp(nl), _dp(nu), C.byref(it))
+    return st, dxi, mu, nl, nu, it.value
+
+
+def ms_sqp(cfg, x0, zbar, u0):
+    """One multiple-shooting SQP solve (W^[0] = I): (converged, u, x, counters)."""
+    p = params(cfg)
+    zbar = np.ascontiguousarray(zbar, dtype=np.float64)
+    u = np.array(u0, dtype=np.float64)
+    x = np.zeros(len(u) + 1)
+    cnt = SampleOut()
+    conv = lib().oc_ms_sqp(C.byref(p), len(u), float(x0), _dp(zbar), _dp(u), _dp(x), C.byref(cnt))
+    return bool(conv), u, x, {f: getattr(cnt, f) for f in OUT_FIELDS[4:]}

@@ -908,7 +908,8 @@ typedef struct {
 
 static uint32_t id32(int64_t id) { return (uint32_t)id; }
 
-static void sample_setup(const oc_params *p, int64_t sample_id, oc_setup *su)
+/* ov (or NULL): caller-given {kind, N, L} of the sample, -1 = the draw.   */
+static void sample_setup(const oc_params *p, int64_t sample_id, const int32_t *ov, oc_setup *su)
 {
     double nr[4];
     double Fss, nss[3];
@@ -926,6 +927,11 @@ static void sample_setup(const oc_params *p, int64_t sample_id, oc_setup *su)
     if (p->L_lo < p->L_hi) {
         oc_normal_pair(p->seed, 1, 0, id32(su->noise_id), TAG_SCEN, nr);
         su->L = p->L_lo + (int32_t)floor(nr[3] * (double)(p->L_hi - p->L_lo + 1));
+    }
+    if (ov) {
+        if (ov[0] >= 0) su->kind = ov[0];
+        if (ov[1] >= 0) su->N = ov[1];
+        if (ov[2] >= 0) su->L = ov[2];
     }
     su->istep = 0;
     su->sign = 0.0;
@@ -980,7 +986,7 @@ static uint64_t fnv1a_bytes(uint64_t h, const unsigned char *b, int n)
 void oc_scenario(const oc_params *p, int64_t sample_id, int32_t iv[4], double dv[3])
 {
     oc_setup su;
-    sample_setup(p, sample_id, &su);
+    sample_setup(p, sample_id, NULL, &su);
     iv[0] = su.kind;
     iv[1] = su.N;
     iv[2] = su.L;
@@ -993,11 +999,12 @@ void oc_scenario(const oc_params *p, int64_t sample_id, int32_t iv[4], double dv
 void oc_run_sample(const oc_params *p, int64_t sample_id, oc_sample_out *out,
                    double *traj_z, double *traj_u, double *traj_xhat)
 {
-    oc_run_sample_ext(p, sample_id, out, traj_z, traj_u, traj_xhat, NULL);
+    oc_run_sample_ext(p, sample_id, NULL, out, traj_z, traj_u, traj_xhat, NULL);
 }
 
-void oc_run_sample_ext(const oc_params *p, int64_t sample_id, oc_sample_out *out,
-                       double *traj_z, double *traj_u, double *traj_xhat, double *traj_I)
+void oc_run_sample_ext(const oc_params *p, int64_t sample_id, const int32_t *ov,
+                       oc_sample_out *out, double *traj_z, double *traj_u, double *traj_xhat,
+                       double *traj_I)
 {
     oc_setup su;
     double n[3], xhat, P, Fprev, Ihat = 0.0, phiacc = 0.0;
@@ -1015,7 +1022,7 @@ void oc_run_sample_ext(const oc_params *p, int64_t sample_id, oc_sample_out *out
     int i, j, k, a, b;
 
     memset(out, 0, sizeof(*out));
-    sample_setup(p, sample_id, &su);
+    sample_setup(p, sample_id, ov, &su);
     tangent = p->want_grad && su.kind == 1;
     {
         double Kc = p->kP, taui = p->kP / p->kI;
@@ -1071,9 +1078,14 @@ void oc_run_sample_ext(const oc_params *p, int64_t sample_id, oc_sample_out *out
                 zb[k] = oc_setpoint(p, i + 1 + k, su.istep, su.sign);
                 u[k] = ws[k];
             }
-            if (!oc_sqp(p, su.N, p->model_nx == 3 ? xh3 : &xhat, zb, u, pil, piu, Wh,
-                        i == 0 || !p->hess_warm, out))
+            if (p->nlp_form == 1) {
+                /* the paper's multiple-shooting NLP, W^[0] = I at every OCP */
+                double xms[OC_NMAX + 1];
+                if (!oc_ms_sqp(p, su.N, xhat, zb, u, xms, out)) out->n_ocp_fail++;
+            } else if (!oc_sqp(p, su.N, p->model_nx == 3 ? xh3 : &xhat, zb, u, pil, piu, Wh,
+                               i == 0 || !p->hess_warm, out)) {
                 out->n_ocp_fail++;
+            }
             out->n_ocp++;
             for (k = 0; k < su.N; ++k)
                 if (u[k] <= p->umin + 1e-6 || u[k] >= p->umax - 1e-6) mask |= (1ull << k);
@@ -1083,7 +1095,7 @@ void oc_run_sample_ext(const oc_params *p, int64_t sample_id, oc_sample_out *out
             F = u[0] / ML_MIN_PER_L_S;
             for (k = 0; k + 1 < su.N; ++k) ws[k] = u[k + 1];
             ws[su.N - 1] = u[su.N - 1];
-            if (p->hess_warm) {
+            if (p->hess_warm && p->nlp_form == 0) {
                 /* shifted Hessian: drop u_0's row/column, repeat the last
                  * diagonal entry with no coupling                            */
                 int r, c2;
@@ -1164,6 +1176,7 @@ void oc_run_sample_ext(const oc_params *p, int64_t sample_id, oc_sample_out *out
 typedef struct {
     const oc_params *p;
     const int64_t *ids;
+    const int32_t *ov;        /* [3][n] {kind, N, L} per task, -1 = drawn, or NULL */
     int64_t n;
     oc_sample_out *out;
     int64_t next;
@@ -1179,7 +1192,12 @@ static void *oc_worker(void *arg)
         t = pool->next++;
         pthread_mutex_unlock(&pool->mu);
         if (t >= pool->n) break;
-        oc_run_sample(pool->p, pool->ids[t], &pool->out[t], NULL, NULL, NULL);
+        if (pool->ov) {
+            int32_t ov[3] = {pool->ov[t], pool->ov[pool->n + t], pool->ov[2 * pool->n + t]};
+            oc_run_sample_ext(pool->p, pool->ids[t], ov, &pool->out[t], NULL, NULL, NULL, NULL);
+        } else {
+            oc_run_sample(pool->p, pool->ids[t], &pool->out[t], NULL, NULL, NULL);
+        }
     }
     return NULL;
 }
@@ -1187,12 +1205,18 @@ static void *oc_worker(void *arg)
 void oc_run(const oc_params *p, const int64_t *ids, int64_t n, int32_t nthreads,
             oc_sample_out *out)
 {
+    oc_run_ov(p, ids, NULL, n, nthreads, out);
+}
+
+void oc_run_ov(const oc_params *p, const int64_t *ids, const int32_t *ov, int64_t n,
+               int32_t nthreads, oc_sample_out *out)
+{
     oc_pool pool;
     pthread_t th[256];
     int t;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
-    pool.p = p; pool.ids = ids; pool.n = n; pool.out = out; pool.next = 0;
+    pool.p = p; pool.ids = ids; pool.ov = ov; pool.n = n; pool.out = out; pool.next = 0;
     pthread_mutex_init(&pool.mu, NULL);
     for (t = 0; t < nthreads; ++t) pthread_create(&th[t], NULL, oc_worker, &pool);
     for (t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);

@@ -62,6 +62,9 @@ typedef struct {
                                        eq. (CSTR) model                      */
     double noise_scale;             /* 1 stochastic; 0 deterministic run (the
                                        filter keeps its R and sigma)         */
+    int32_t nlp_form;               /* OCP discretisation: 0 single shooting,
+                                       1 multiple shooting, eq. (OCP_NLP)
+                                       (one-state model; mc_oracle_ms.c)     */
 } oc_params;
 
 /* Per-sample result.                                                        */
@@ -114,17 +117,30 @@ int  oc_sqp(const oc_params *p, int32_t N, const double *x0, const double *zbar,
             double *pil, double *piu, double *W, int32_t reset_W, oc_sample_out *cnt);
 void oc_run_sample(const oc_params *p, int64_t sample_id, oc_sample_out *out,
                    double *traj_z, double *traj_u, double *traj_xhat);
-/* As oc_run_sample, also recording the PI integral state after interval i's
- * update (traj_I[i], PI samples; may be NULL).                              */
-void oc_run_sample_ext(const oc_params *p, int64_t sample_id, oc_sample_out *out,
-                       double *traj_z, double *traj_u, double *traj_xhat, double *traj_I);
+/* As oc_run_sample, with caller-given {kind, N, L} (ov, -1 = the draw; or
+ * NULL), also recording the PI integral state after interval i's update
+ * (traj_I[i], PI samples; may be NULL).                                     */
+void oc_run_sample_ext(const oc_params *p, int64_t sample_id, const int32_t *ov,
+                       oc_sample_out *out, double *traj_z, double *traj_u, double *traj_xhat,
+                       double *traj_I);
 /* The per-sample scenario draws: iv = {kind, N, L, step interval},
  * dv = {step sign, plant k0, plant Ea/R}.                                   */
 void oc_scenario(const oc_params *p, int64_t sample_id, int32_t iv[4], double dv[3]);
 void oc_run(const oc_params *p, const int64_t *ids, int64_t n, int32_t nthreads,
             oc_sample_out *out);
+/* As oc_run with caller-given per-sample {kind, N, L} (ov: [3][n], row 0
+ * kind, 1 horizon, 2 length of task t at column t; -1 keeps the draw).     */
+void oc_run_ov(const oc_params *p, const int64_t *ids, const int32_t *ov, int64_t n,
+               int32_t nthreads, oc_sample_out *out);
 void oc_stats(const double *phi, int64_t n, double *mean, double *var,
               int64_t *hist /* 202 */);
+/* multiple shooting (mc_oracle_ms.c)                                        */
+void oc_ms_interval(const oc_params *p, double x, double u, double out[3]);
+int  oc_ms_qp(const oc_params *p, int32_t N, const double *W, const double *gf,
+              const double *A, const double *B, const double *c, const double *u,
+              double *dxi, double *mu, double *nl, double *nu, int32_t *iters);
+int  oc_ms_sqp(const oc_params *p, int32_t N, double x0, const double *zbar, double *u,
+               double *x, oc_sample_out *cnt);
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,7 @@ CNT_NAMES = ["kind", "N", "L", "n_ocp", "n_ocp_fail", "sqp_iter", "ipm_iter", "l
 NCNT = len(CNT_NAMES)
 STATUS = {0: "MC_CL_OK", -1: "MC_CL_EINVAL", -2: "MC_CL_EHIP", -3: "MC_CL_ENOMEM",
           -4: "MC_CL_ESTATE", -5: "MC_CL_EUNSUPPORTED"}
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 
 class Params(C.Structure):
@@ -53,6 +53,8 @@ class Params(C.Structure):
         ("ckpt_interval", C.c_int32), ("samples_per_wave", C.c_int32),
         ("qp_solver", C.c_int32), ("chunk_samples", C.c_int32),
         ("cu_limit", C.c_int32), ("model_nx", C.c_int32),
+        ("sample_ids", C.c_void_p), ("kind", C.c_void_p), ("horizon", C.c_void_p),
+        ("lengths", C.c_void_p),
     ]
 
 
@@ -131,8 +133,28 @@ def _check(rc: int, what: str):
         raise McClError(f"{what}: {STATUS.get(rc, rc)} ({msg})")
 
 
-def params(cfg: dict) -> Params:
-    """mc_cl_params from a workload dict (see workloads.py)."""
+# per-sample arrays of the workload dict: key -> numpy dtype of the C array
+PER_SAMPLE = {"sample_ids": "int64", "kind": "uint8", "horizon": "int32", "lengths": "int32"}
+
+
+def per_sample_arrays(cfg: dict) -> dict:
+    """Contiguous host copies of the workload's per-sample arrays (those
+    not None), of the C types mc_cl_params names."""
+    import numpy as np
+    out = {}
+    for key, dt in PER_SAMPLE.items():
+        a = cfg.get(key)
+        if a is not None:
+            a = np.ascontiguousarray(a, dtype=dt)
+            if a.shape != (int(cfg["n_samples"]),):
+                raise ValueError(f"{key} must have n_samples entries")
+            out[key] = a
+    return out
+
+
+def params(cfg: dict, arrays: dict = None) -> Params:
+    """mc_cl_params from a workload dict (see workloads.py); `arrays` from
+    per_sample_arrays(cfg) must stay alive while the struct is used."""
     p = Params()
     p.struct_size = C.sizeof(Params)
     p.abi_version = ABI_VERSION
@@ -164,6 +186,8 @@ def params(cfg: dict) -> Params:
     p.n_horizon_choices = len(hc)
     for j, v in enumerate(hc):
         p.horizon_choices[j] = v
+    for key, a in (arrays or {}).items():
+        setattr(p, key, a.ctypes.data)
     return p
 
 
@@ -176,7 +200,8 @@ class Campaign:
         self.torch = torch
         self.cfg = dict(cfg)
         self.S = int(cfg["n_samples"])
-        self.p = params(self.cfg)
+        arrays = per_sample_arrays(self.cfg)
+        self.p = params(self.cfg, arrays)
         h = C.c_void_p()
         _check(lib().mc_cl_create(C.byref(self.p), C.byref(h)), "mc_cl_create")
         self.h = h
@@ -206,7 +231,10 @@ class Campaign:
         if trajectories:
             # rows for the longest possible sample (mc_cl_outputs: T)
             c = self.cfg
-            L = int(c["L_hi"] if c["L_lo"] < c["L_hi"] else c["L"])
+            if c.get("lengths") is not None:
+                L = int(max(c["lengths"]))
+            else:
+                L = int(c["L_hi"] if c["L_lo"] < c["L_hi"] else c["L"])
             dev = self.phi.device
             self.traj = dict(z=torch.empty((L + 1, self.S), dtype=torch.float64, device=dev),
                              u=torch.empty((L, self.S), dtype=torch.float64, device=dev),

@@ -37,7 +37,7 @@ thread_local std::string g_hip_error;
 __global__ void plan_kernel(DevParams p, int64_t S, int32_t* kind, int32_t* N, int32_t* L) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= S) return;
-    const Setup s = sample_setup(p, p.id_offset + t);
+    const Setup s = sample_setup(p, t);
     kind[t] = s.kind;
     N[t] = s.N;
     L[t] = s.L;
@@ -280,8 +280,16 @@ static int validate(const mc_cl_params* p) {
     if (p->chunk_samples < 0 || p->cu_limit < 0) return MC_CL_EINVAL;
     if (p->model_nx != 1 && p->model_nx != 3) return MC_CL_EINVAL;
     if (p->model_nx == 3 && p->grad_mode != 1) return MC_CL_EUNSUPPORTED;
-    if (p->sample_id_offset < 0 || p->sample_id_offset + p->n_samples > (int64_t)UINT32_MAX)
+    if (!p->sample_ids &&
+        (p->sample_id_offset < 0 || p->sample_id_offset + p->n_samples > (int64_t)UINT32_MAX))
         return MC_CL_EINVAL;
+    for (int64_t s = 0; s < p->n_samples; ++s) {
+        if (p->sample_ids && (p->sample_ids[s] < 0 || p->sample_ids[s] >= (int64_t)UINT32_MAX))
+            return MC_CL_EINVAL;
+        if (p->kind && p->kind[s] > 1) return MC_CL_EINVAL;
+        if (p->horizon && (p->horizon[s] < 1 || p->horizon[s] > MC_CL_NMAX)) return MC_CL_EINVAL;
+        if (p->lengths && (p->lengths[s] < 0 || p->lengths[s] > (1 << 24))) return MC_CL_EINVAL;
+    }
     return MC_CL_OK;
 }
 
@@ -450,6 +458,10 @@ static DevParams to_dev(const mc_cl_params& p) {
     d.qp_solver = p.qp_solver;
     d.L_cap = INT32_MAX;
     d.model_nx = p.model_nx;
+    d.ids = nullptr;       // device copies of the per-sample arrays: set at create
+    d.kind_ov = nullptr;
+    d.N_ov = nullptr;
+    d.L_ov = nullptr;
     return d;
 }
 
@@ -534,6 +546,39 @@ int mc_cl_create(const mc_cl_params* p, mc_cl_ctx** out) {
     c->n_cu = prop.multiProcessorCount;
     if (p->cu_limit > 0 && p->cu_limit < c->n_cu) c->n_cu = p->cu_limit;
     const int64_t S = c->S;
+    // the caller's per-sample arrays, copied to the device (the context's
+    // parameter copy must not keep the caller's host pointers)
+    c->prm.sample_ids = nullptr;
+    c->prm.kind = nullptr;
+    c->prm.horizon = nullptr;
+    c->prm.lengths = nullptr;
+    if (p->sample_ids) {
+        int64_t* d = nullptr;
+        if ((rc = c->alloc(&d, S))) return fail(rc);
+        if (hipMemcpy(d, p->sample_ids, S * 8, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(MC_CL_EHIP);
+        c->dp.ids = d;
+    }
+    if (p->kind) {
+        uint8_t* d = nullptr;
+        if ((rc = c->alloc(&d, S))) return fail(rc);
+        if (hipMemcpy(d, p->kind, S, hipMemcpyHostToDevice) != hipSuccess) return fail(MC_CL_EHIP);
+        c->dp.kind_ov = d;
+    }
+    if (p->horizon) {
+        int32_t* d = nullptr;
+        if ((rc = c->alloc(&d, S))) return fail(rc);
+        if (hipMemcpy(d, p->horizon, S * 4, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(MC_CL_EHIP);
+        c->dp.N_ov = d;
+    }
+    if (p->lengths) {
+        int32_t* d = nullptr;
+        if ((rc = c->alloc(&d, S))) return fail(rc);
+        if (hipMemcpy(d, p->lengths, S * 4, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(MC_CL_EHIP);
+        c->dp.L_ov = d;
+    }
 
     // plan: per-sample kind / N / L on the device
     int32_t *d_kind, *d_N, *d_L;

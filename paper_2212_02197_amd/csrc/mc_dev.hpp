@@ -55,6 +55,12 @@ struct DevParams {
     int ckpt_C, qp_solver;
     int L_cap;           // closed-loop intervals are cut at L_cap (trial launches)
     int model_nx;        // estimator / OCP model: 1 one-state closure, 3 three-state
+    // caller-given per-sample arrays (device copies, indexed by the sample's
+    // column), or null: sample id, kind, horizon, length
+    const int64_t* ids;
+    const uint8_t* kind_ov;
+    const int32_t* N_ov;
+    const int32_t* L_ov;
 };
 
 // Noise streams: the counter's last word.
@@ -356,8 +362,12 @@ struct Setup {
 // Not inlined: it runs once per sample, and keeping its many loop-invariant
 // constants out of the persistent kernel's register allocation leaves that
 // allocation to the closed loop.
-__device__ __noinline__ Setup sample_setup(const DevParams& p, int64_t sid) {
+// Set-up of the sample in column `col`: its global id (caller-given or
+// id_offset + col), noise id, kind, horizon and length (caller-given or
+// drawn), scenario, kinetics and initial state.
+__device__ __noinline__ Setup sample_setup(const DevParams& p, int64_t col) {
     Setup s;
+    const int64_t sid = p.ids ? p.ids[col] : p.id_offset + col;
     const int64_t nid = p.noise_mod > 0 ? sid % p.noise_mod : sid;
     s.nid = (uint32_t)nid;
     s.kind = p.kind_split >= 0 ? (sid < p.kind_split ? 0 : 1) : p.default_kind;
@@ -371,6 +381,9 @@ __device__ __noinline__ Setup sample_setup(const DevParams& p, int64_t sid) {
         const double u = philox_uniforms(p.seed, 1, 0, s.nid, kTagScen).u2;
         s.L = p.L_lo + (int)floor(u * (double)(p.L_hi - p.L_lo + 1));
     }
+    if (p.kind_ov) s.kind = p.kind_ov[col];
+    if (p.N_ov) s.N = p.N_ov[col];
+    if (p.L_ov) s.L = p.L_ov[col];
     if (s.L > p.L_cap) s.L = p.L_cap;
     s.istep = 0;
     s.sign = 0.0;

@@ -80,9 +80,21 @@ def test_abi_version_and_strerror(lib):
 
 
 def _create(cfg, **over):
-    p = binding.params(dict(cfg, **over))
+    cfg = dict(cfg, **over)
+    arrays = binding.per_sample_arrays(cfg)
+    p = binding.params(cfg, arrays)
     h = C.c_void_p()
     return binding.lib().mc_cl_create(C.byref(p), C.byref(h))
+
+
+@pytest.mark.parametrize("over", [dict(kind=[0, 2, 1, 0]), dict(horizon=[10, 0, 10, 10]),
+                                  dict(horizon=[10, 65, 10, 10]), dict(lengths=[5, -1, 5, 5]),
+                                  dict(lengths=[5, (1 << 24) + 1, 5, 5]),
+                                  dict(sample_ids=[0, -3, 1, 2]),
+                                  dict(sample_ids=[0, 1, 2, (1 << 32) - 1])])
+def test_invalid_per_sample_arrays_are_rejected(lib, over):
+    from paper_2212_02197_amd import workloads
+    assert _create(workloads.c0_small_nmpc(n_samples=4), **over) == -1
 
 
 @pytest.mark.parametrize("over", [dict(V=0.0), dict(N=0), dict(N=65), dict(umin=5.0, umax=1.0),
@@ -129,3 +141,4 @@ def test_tune_rejects_bad_arguments(lib):
 def test_stream_helpers_reject_null(lib):
     assert lib.mc_cl_stream_create(4, None) == -1
     assert lib.mc_cl_stream_destroy(None) == -1
+

@@ -1,11 +1,19 @@
 """Parity of the HIP path (through the C-ABI) with the CPU oracle.
 
 Tolerances: per-sample Phi relative 1e-9 for PI and 1e-6 for NMPC; mean and
-variance of each controller's Phi relative 1e-8; integer outputs (OCP counts,
-horizon, length, histogram) exact; every sample whose active-set signature
-differs from the oracle's is reported (a "flip").  Sizes: small cases span
-several wavefront groups and a ragged tail; paper-scale configurations are
-checked on sampled sample ids computed by the oracle one by one.
+variance of each controller's Phi relative 1e-8; integer outputs (kind,
+horizon, length, OCP counts, histogram) exact; every sample whose active-set
+signature differs from the oracle's is a "flip" and fails the comparison.
+
+NMPC cases run the SQP at the KKT tolerance EPS = 1e-10: at the throughput
+default (1e-6, the NMPC per-sample bar itself) two roundings of the same
+iteration can stop one SQP iteration apart.  At 1e-10 the oracle's two
+mathematically equal gradient orders agree within 1e-8 on every sample of
+these cases, except on c3 with its plant-model mismatch (see
+test_c3_uneven_sampled).  Sizes: small cases span several wavefront groups
+and a ragged tail; paper-scale configurations run strided subsets of their
+sample ids (the sample_ids array) at full shape, in the launch shape the
+benchmark uses.
 """
 import os
 import sys
@@ -23,6 +31,7 @@ import oracle  # noqa: E402
 from paper_2212_02197_amd import binding, workloads as W  # noqa: E402
 
 NTHREADS = min(16, len(os.sched_getaffinity(0)))
+EPS = 1e-10
 
 
 def gpu_run(cfg, traj=False):
@@ -37,14 +46,25 @@ def gpu_run(cfg, traj=False):
     return phi, stats, ps, tr
 
 
+def sample_ids(cfg):
+    if cfg.get("sample_ids") is not None:
+        return np.asarray(cfg["sample_ids"], dtype=np.int64)
+    return np.arange(cfg["n_samples"], dtype=np.int64) + cfg.get("sample_id_offset", 0)
+
+
 def oracle_run(cfg, ids=None):
     if ids is None:
-        ids = np.arange(cfg["n_samples"]) + cfg.get("sample_id_offset", 0)
-    return oracle.run(cfg, ids=np.asarray(ids, dtype=np.int64), nthreads=NTHREADS)
+        ids = sample_ids(cfg)
+    return oracle.run(cfg, ids=np.asarray(ids, dtype=np.int64), nthreads=NTHREADS,
+                      kind=cfg.get("kind"), horizon=cfg.get("horizon"),
+                      lengths=cfg.get("lengths"))
 
 
 def compare(phi_g, ps_g, ref, sel=None, tag=""):
-    """Element-wise comparison; returns (flips, max rel err per kind)."""
+    """Element-wise comparison at the bar: every NMPC sample within 1e-6,
+    every PI sample within 1e-9, flipped or not.  Flips (an input within
+    1e-6 mL/min of a bound in one run and not in the other at some OCP) are
+    listed with their Phi errors.  Returns the max rel error per kind."""
     if sel is None:
         sel = np.arange(len(ref["phi"]))
     pg = phi_g[sel]
@@ -59,62 +79,81 @@ def compare(phi_g, ps_g, ref, sel=None, tag=""):
         if not m.any():
             continue
         bad = np.nonzero(m & (rel > tol))[0]
-        bad_noflip = [b for b in bad if b not in set(flips)]
         out[k] = float(rel[m].max())
         print(f"{tag} kind {k}: n={m.sum()} max rel {rel[m].max():.3e} flips {len(flips)} "
-              f"bad {len(bad)}", flush=True)
-        assert not bad_noflip, (tag, k, bad_noflip[:5], rel[bad_noflip[:5]])
-    # a flip may carry a larger Phi difference, but must stay rare
-    assert len(flips) <= max(1, len(sel) // 50), (tag, flips)
-    return flips, out
+              f"above the bar {len(bad)}", flush=True)
+        assert len(bad) == 0, (tag, k, bad[:5], rel[bad[:5]])
+    # counters that rounding may move by one iteration are reported, not
+    # compared; resets of W are rare events and must agree in total
+    for f in ("n_ocp_fail", "sqp_iter", "ls_trials", "ls_cap", "bfgs_skip", "bfgs_reset"):
+        d = ps_g[f][sel].astype(np.int64) - ref[f]
+        print(f"{tag} counter {f}: gpu {ps_g[f][sel].sum()} oracle {ref[f].sum()} "
+              f"max |diff| {np.abs(d).max()}", flush=True)
+    assert ps_g["bfgs_reset"][sel].sum() == ref["bfgs_reset"].sum(), tag
+    for j in flips:
+        print(f"{tag} flip: sample {j} kind {kind[j]} Phi rel {rel[j]:.2e}", flush=True)
+    assert len(flips) <= max(1, len(sel) // 50), (tag, flips[:10])
+    return out
+
+
+def check_stats(stats, ref, kinds=(0, 1), hist=True):
+    """Mean and variance of each controller's Phi within 1e-8 relative of the
+    oracle's exact sums; histogram counts exact."""
+    for k in kinds:
+        m = ref["kind"] == k
+        mo, vo, ho = oracle.stats(ref["phi"][m])
+        assert stats["count"][k] == m.sum()
+        print(f"stats kind {k}: n={m.sum()} mean {stats['mean'][k]:.12g} rel "
+              f"{abs(stats['mean'][k] - mo) / mo:.2e} var rel "
+              f"{abs(stats['var'][k] - vo) / vo:.2e}", flush=True)
+        assert stats["mean"][k] == pytest.approx(mo, rel=1e-8)
+        assert stats["var"][k] == pytest.approx(vo, rel=1e-8)
+        if hist:
+            np.testing.assert_array_equal(stats["hist"][k], ho)
 
 
 def test_c0_small_nmpc_full():
     # two wavefronts of 32 samples (the automatic plan of so small a campaign
     # would give each sample a wavefront of its own): cooperative visits over
     # many samples and the paired line search
-    cfg = W.c0_small_nmpc(samples_per_wave=32)
+    cfg = W.c0_small_nmpc(samples_per_wave=32, sqp_eps=EPS)
     phi, stats, ps, _ = gpu_run(cfg)
     ref = oracle_run(cfg)
     compare(phi, ps, ref, tag="c0")
-    # counters of the SQP path agree exactly where no active set flipped
-    same = ps["ashash"] == ref["ashash"]
-    for f in ("n_ocp_fail", "sqp_iter", "ls_trials"):
-        d = np.abs(ps[f][same] - ref[f][same])
-        print("c0 counter", f, "max |diff|", d.max(), flush=True)
-    m, v, h = oracle.stats(ref["phi"])
-    assert stats["count"] == [64, 0]
-    assert stats["mean"][0] == pytest.approx(m, rel=1e-8)
-    assert stats["var"][0] == pytest.approx(v, rel=1e-8)
+    check_stats(stats, ref, kinds=(0,))
 
 
 def test_c0_forward_sensitivity_mode():
-    cfg = W.c0_small_nmpc(grad_mode=0, n_samples=40)
+    cfg = W.c0_small_nmpc(grad_mode=0, n_samples=40, sqp_eps=EPS)
     phi, stats, ps, _ = gpu_run(cfg)
     ref = oracle_run(cfg)
     compare(phi, ps, ref, tag="c0-fwd")
 
 
 def test_c1_pi_half_sampled():
-    # paper-scale PI half: 640 of the 30,000 PI samples, full L = 600, Ns = 20
-    cfg = W.c1_paper_scale(n_samples=640, sample_id_offset=30000)
+    # paper-scale PI half: 640 strided ids of the 30,000 PI samples, full
+    # L = 600, Ns = 20
+    ids = 30000 + np.arange(0, 30000, 46)[:640]
+    cfg = W.c1_paper_scale(n_samples=len(ids), sample_ids=ids)
     phi, stats, ps, _ = gpu_run(cfg)
     ref = oracle_run(cfg)
     compare(phi, ps, ref, tag="c1-pi")
-    m, v, h = oracle.stats(ref["phi"])
-    assert stats["count"] == [0, 640]
-    assert stats["mean"][1] == pytest.approx(m, rel=1e-8)
-    assert stats["var"][1] == pytest.approx(v, rel=1e-8)
-    np.testing.assert_array_equal(stats["hist"][1], h)
+    check_stats(stats, ref, kinds=(1,))
 
 
-def test_c1_nmpc_sampled_paper_horizon():
-    # paper-scale NMPC: N = 60, Nc = 5, L = 600, Ns = 20, 6 samples
-    cfg = W.c1_paper_scale(n_samples=6, sample_id_offset=0)
+def test_c1_nmpc_production_shape():
+    # paper-scale NMPC (N = 60, Nc = 5, L = 600, Ns = 20) on 256 strided ids
+    # of the 30,000, in the benchmark's launch shape: 30 samples per
+    # wavefront (NMAX 64, multi-sample cooperative visits, the paired line
+    # search), 8 full wavefronts and a ragged ninth of 16
+    ids = np.arange(0, 30000, 117)[:256]
+    cfg = W.c1_paper_scale(n_samples=len(ids), sample_ids=ids, samples_per_wave=30,
+                           sqp_eps=EPS)
     phi, stats, ps, _ = gpu_run(cfg)
     ref = oracle_run(cfg)
+    assert ps["n_ocp"].tolist() == [600] * len(ids)
     compare(phi, ps, ref, tag="c1-nmpc")
-    assert ps["n_ocp"].tolist() == [600] * 6
+    check_stats(stats, ref, kinds=(0,))
 
 
 def test_deterministic_runs_and_trajectories():
@@ -135,56 +174,113 @@ def test_deterministic_runs_and_trajectories():
     assert phi[0] < phi[1]  # NMPC beats PI in the deterministic case
 
 
-def conditioned(cfg, ids, ref):
-    """Samples on which the oracle agrees with itself: the same campaign with
-    the other (mathematically equal) gradient evaluation order, which moves
-    every result by rounding only.  A sample is well conditioned when the two
-    oracle runs agree within 1e-8 relative and no active set flips; on the
-    others the closed loop amplifies rounding (model-plant mismatch, SQP
-    iteration caps), and their GPU/oracle distance is bounded by the
-    oracle's own."""
-    alt = oracle_run(dict(cfg, grad_mode=1 - cfg["grad_mode"]), ids)
-    rel_self = np.abs(alt["phi"] - ref["phi"]) / np.abs(ref["phi"])
-    good = (rel_self <= 1e-8) & (alt["ashash"] == ref["ashash"])
-    return good, rel_self
-
-
-def compare_conditioned(cfg, phi, ps, ref, tag):
-    ids = np.arange(cfg["n_samples"]) + cfg["sample_id_offset"]
-    good, rel_self = conditioned(cfg, ids, ref)
-    g = np.nonzero(good)[0]
-    print(f"{tag}: {good.sum()} of {len(good)} samples well conditioned", flush=True)
-    compare(phi, ps, {k: v[g] for k, v in ref.items()}, sel=g, tag=tag + " (conditioned)")
-    rel = np.abs(phi - ref["phi"]) / np.abs(ref["phi"])
-    bad = np.nonzero(~good)[0]
-    if len(bad):
-        print(f"{tag} ill-conditioned: gpu/oracle rel {np.array2string(rel[bad], precision=2)}"
-              f" oracle/oracle rel {np.array2string(rel_self[bad], precision=2)}", flush=True)
-        # no worse than the oracle's own spread on those samples (x100 margin)
-        assert np.all(rel[bad] <= 100 * np.maximum(rel_self[bad], 1e-6))
-    return good
-
-
 def test_c3_uneven_sampled():
-    # uneven batch: N ~ U{10, 25, 50}, L ~ U{100..400}, perturbed kinetics
-    cfg = W.c3_uneven(n_samples=24, sample_id_offset=1000, samples_per_wave=8)
-    phi, stats, ps, _ = gpu_run(cfg)
+    # Uneven batch at full shape: N ~ U{10, 25, 50}, L ~ U{100..400}, plant
+    # kinetics perturbed by lognormal factors (sigma 0.05), 128 strided ids.
+    # The plant-model mismatch leaves some closed loops bang-bang between the
+    # input bounds, where a rounding difference grows from interval to
+    # interval: on those the oracle's two gradient orders (equal up to
+    # rounding) themselves end more than 1e-6 apart, so Phi is not determined
+    # at the per-sample bar by the inputs.  Determined samples (the two
+    # orders within 1e-8, same active sets) must meet the bar.  On each
+    # rounding-sensitive sample the oracle follows itself (outputs z within
+    # 1e-8) up to an interval t; there the GPU's z must stay within 1e-6 of
+    # the oracle's and the cost of eq. (Phi) over intervals 0..t within 1e-6;
+    # its error on the whole closed loop is listed.
+    ids = np.arange(0, 100000, 773)[:128]
+    cfg = W.c3_uneven(n_samples=len(ids), sample_ids=ids, sqp_eps=EPS)
+    phi, stats, ps, tr = gpu_run(cfg, traj=True)
     ref = oracle_run(cfg)
+    alt = oracle_run(dict(cfg, grad_mode=0))
     for f in ("kind", "N", "L", "n_ocp"):
         np.testing.assert_array_equal(ps[f], ref[f], err_msg=f)
-    good = compare_conditioned(cfg, phi, ps, ref, "c3")
-    # model-plant mismatch leaves about half of these samples rounding-sensitive
-    assert good.sum() >= len(good) // 3
-    assert set(ps["N"].tolist()) <= {10, 25, 50}
+    assert set(ps["N"].tolist()) == {10, 25, 50}
+    rel_self = np.abs(alt["phi"] - ref["phi"]) / ref["phi"]
+    det = (rel_self <= 1e-8) & (alt["ashash"] == ref["ashash"])
+    g = np.nonzero(det)[0]
+    print(f"c3: {det.sum()} of {len(det)} samples determined at 1e-8", flush=True)
+    assert det.sum() >= 3 * len(det) // 4
+    compare(phi, ps, {k: v[g] for k, v in ref.items() if k != "ids"}, sel=g, tag="c3 determined")
+    rel = np.abs(phi - ref["phi"]) / ref["phi"]
+    for j in np.nonzero(~det)[0]:
+        cs = dict(cfg, sample_ids=None, n_samples=1)
+        ra = oracle.run_sample(cs, int(ids[j]), traj=True)
+        rb = oracle.run_sample(dict(cs, grad_mode=0), int(ids[j]), traj=True)
+        L = int(ref["L"][j])
+        z_g = tr["z"][:L + 1, j]
+        dz = np.abs(ra["z"] - rb["z"]) > 1e-8 * np.abs(ra["z"])
+        t = int(np.argmax(dz)) if dz.any() else L
+        zb = np.array([oracle.setpoint(cs, i, 0, 0.0) for i in range(t + 1)])
+        pre_o = np.mean((ra["z"][:t + 1] - zb) ** 2)
+        pre_g = np.mean((z_g[:t + 1] - zb) ** 2)
+        ez = np.abs(z_g[:t + 1] - ra["z"][:t + 1]) / ra["z"][:t + 1]
+        print(f"c3 rounding-sensitive id {ids[j]} N {ref['N'][j]} L {L}: oracle follows itself "
+              f"to interval {t}; there z rel {ez.max():.2e}, Phi(0..t) rel "
+              f"{abs(pre_g - pre_o) / pre_o:.2e}; whole loop gpu/oracle Phi rel {rel[j]:.2e}, "
+              f"oracle/oracle {rel_self[j]:.2e}", flush=True)
+        assert ez.max() <= 1e-6, ids[j]
+        assert pre_g == pytest.approx(pre_o, rel=1e-6), ids[j]
+    m, v, _ = oracle.stats(ref["phi"][g])
+    m_g, v_g, _ = oracle.stats(phi[g])
+    assert m_g == pytest.approx(m, rel=1e-8) and v_g == pytest.approx(v, rel=1e-8)
+
+
+def test_c3_all_horizon_classes_without_mismatch():
+    # c3's horizons and ragged lengths at full shape with the nominal plant
+    # kinetics (no model-plant mismatch): every sample at the bar
+    ids = np.arange(5, 100000, 769)[:128]
+    cfg = W.c3_uneven(n_samples=len(ids), sample_ids=ids, sqp_eps=EPS, kin_lognorm_sigma=0.0)
+    phi, stats, ps, _ = gpu_run(cfg)
+    ref = oracle_run(cfg)
+    assert set(ps["N"].tolist()) == {10, 25, 50}
+    assert len(set(ps["L"].tolist())) > 60
+    compare(phi, ps, ref, tag="c3 nominal kinetics")
+    check_stats(stats, ref, kinds=(0,))
+
+
+def test_c4_mixed_strided_pairs():
+    # c4's two halves: 128 strided NMPC ids (N = 25) and the PI samples that
+    # share their noise ids, L = 300, +-10 % setpoint step
+    nm = np.arange(11, 500000, 3901)[:128]
+    ids = np.concatenate([nm, nm + 500000])
+    cfg = W.c4_mixed(n_samples=len(ids), sample_ids=ids, sqp_eps=EPS)
+    phi, stats, ps, _ = gpu_run(cfg)
+    ref = oracle_run(cfg)
+    assert ps["kind"].tolist() == [0] * 128 + [1] * 128
+    compare(phi, ps, ref, tag="c4")
+    check_stats(stats, ref)
 
 
 def test_c4_mixed_across_the_split():
     # ids 499,990 .. 500,009: ten NMPC (N = 25) then ten PI on shared noise ids
-    cfg = W.c4_mixed(n_samples=20, sample_id_offset=499990)
+    cfg = W.c4_mixed(n_samples=20, sample_id_offset=499990, sqp_eps=EPS)
     phi, stats, ps, _ = gpu_run(cfg)
     ref = oracle_run(cfg)
-    compare_conditioned(cfg, phi, ps, ref, "c4")
+    compare(phi, ps, ref, tag="c4 split")
     assert ps["kind"].tolist() == [0] * 10 + [1] * 10
+
+
+def test_caller_given_kind_horizon_and_length():
+    # per-sample arrays in place of the campaign's rules: a PI sample among
+    # NMPC ones, horizons of all three classes, lengths 0..13, repeated ids
+    ids = np.array([3, 3, 17, 40, 41, 99, 5, 8])
+    kind = np.array([0, 1, 0, 0, 1, 0, 0, 1], dtype=np.uint8)
+    hor = np.array([10, 10, 20, 50, 7, 64, 1, 33], dtype=np.int32)
+    lens = np.array([7, 7, 13, 0, 9, 4, 11, 2], dtype=np.int32)
+    cfg = W.c0_small_nmpc(n_samples=len(ids), sample_ids=ids, kind=kind, horizon=hor,
+                          lengths=lens, sqp_eps=EPS)
+    phi, stats, ps, tr = gpu_run(cfg, traj=True)
+    ref = oracle_run(cfg)
+    np.testing.assert_array_equal(ps["kind"], kind)
+    np.testing.assert_array_equal(ps["N"][kind == 0], hor[kind == 0])
+    np.testing.assert_array_equal(ps["L"], lens)
+    compare(phi, ps, ref, tag="caller arrays")
+    assert tr["z"].shape == (lens.max() + 1, len(ids))
+    for j in range(len(ids)):
+        r = oracle.run_sample(dict(cfg, sample_ids=None, kind_split=-1,
+                                   default_kind=int(kind[j]), N=int(hor[j]), L=int(lens[j]),
+                                   n_samples=1), int(ids[j]), traj=True)
+        np.testing.assert_allclose(tr["z"][:lens[j] + 1, j], r["z"], rtol=1e-9)
 
 
 def test_pi_gradient_against_oracle_tangent():
@@ -236,7 +332,7 @@ def test_repeat_runs_are_bitwise_identical():
                                   dict(sqp_max_iter=0), dict(n_samples=65, L=3),
                                   dict(hess_warm=0, L=4)])
 def test_edge_cases(over):
-    cfg = W.c0_small_nmpc(**dict(dict(n_samples=5, L=5), **over))
+    cfg = W.c0_small_nmpc(**dict(dict(n_samples=5, L=5, sqp_eps=EPS), **over))
     phi, stats, ps, _ = gpu_run(cfg)
     ref = oracle_run(cfg)
     compare(phi, ps, ref, tag=f"edge {over}")
@@ -250,7 +346,7 @@ def test_edge_cases(over):
 def test_w_form_qp_solvers(qp):
     # the QP on the BFGS matrix W itself: interior point (0) and active set
     # with interior-point fallback (1); same closed loops as the default
-    cfg = W.c0_small_nmpc(n_samples=24, qp_solver=qp)
+    cfg = W.c0_small_nmpc(n_samples=24, qp_solver=qp, sqp_eps=EPS)
     phi, stats, ps, _ = gpu_run(cfg)
     ref = oracle_run(cfg)
     compare(phi, ps, ref, tag=f"qp_solver {qp}")
@@ -260,15 +356,12 @@ def test_mixed_horizons_share_wave_slots():
     # N ~ U{20, 30}: one NMAX class, so a wavefront's matrix slots are reused
     # by samples of both horizons (entries outside a sample's N x N block
     # must not leak into its QP); several groups and a ragged tail
-    cfg = W.c0_small_nmpc(n_samples=70, L=12, horizon_choices=(20, 30), samples_per_wave=8)
+    cfg = W.c0_small_nmpc(n_samples=70, L=12, horizon_choices=(20, 30), samples_per_wave=8,
+                          sqp_eps=EPS)
     phi, stats, ps, _ = gpu_run(cfg)
     ref = oracle_run(cfg)
     assert set(ps["N"].tolist()) == {20, 30}
-    # a sample whose SQP hits its iteration cap is rounding sensitive (the
-    # oracle's two gradient orders differ by ~3e-6 on one here); this start-up
-    # transient from inlet conditions leaves about a fifth of them so
-    good = compare_conditioned(cfg, phi, ps, ref, "mixed N")
-    assert good.sum() >= len(good) // 2
+    compare(phi, ps, ref, tag="mixed N")
 
 
 def test_pi_autograd_function():
@@ -309,7 +402,7 @@ def test_chunked_graph_run_matches_single_launch():
     # in 5 chunks, each one replay of the captured chunk step: bitwise the
     # single-launch results, on every replay, and the oracle's on a sample
     cfg = W.c4_mixed(n_samples=600, kind_split=300, noise_mod=300, L=12, sp_step_lo=3,
-                     sp_step_hi=9)
+                     sp_step_hi=9, sqp_eps=EPS)
     phi1, st1, ps1, _ = gpu_run(cfg)
     camp = binding.Campaign(dict(cfg, chunk_samples=130))
     outs = []
@@ -392,7 +485,7 @@ def test_tune_keeps_results_and_picks_a_candidate():
 def test_cu_limited_stream_matches_full_device():
     # planning for 16 compute units and running on a stream limited to them
     # changes the launch shape only: results bitwise equal, and the oracle's
-    cfg = W.c0_small_nmpc(n_samples=70, L=6)
+    cfg = W.c0_small_nmpc(n_samples=70, L=6, sqp_eps=EPS)
     phi0, _, ps0, _ = gpu_run(cfg)
     cs = binding.CuStream(16)
     camp = binding.Campaign(dict(cfg, cu_limit=16))
@@ -414,30 +507,24 @@ def test_cu_limited_stream_matches_full_device():
 def test_three_state_c0_full():
     # 64 NMPC samples, N = 10 (the 16-wide horizon class), perturbed
     # steady-state starts; the model matches the plant apart from the noise
-    cfg = W.c0_small_nmpc(model_nx=3, samples_per_wave=16)
+    cfg = W.c0_small_nmpc(model_nx=3, samples_per_wave=16, sqp_eps=EPS)
     phi, stats, ps, _ = gpu_run(cfg)
     ref = oracle_run(cfg)
-    good = compare_conditioned(cfg, phi, ps, ref, "c0-3state")
-    assert good.sum() >= 3 * len(good) // 4
-    m, v, h = oracle.stats(ref["phi"])
-    assert stats["mean"][0] == pytest.approx(m, rel=1e-6)
+    compare(phi, ps, ref, tag="c0-3state")
+    check_stats(stats, ref, kinds=(0,))
 
 
 def test_three_state_all_horizon_classes_and_pi_estimator():
     # horizons 10 / 25 / 50 (all three kernel classes) with ragged lengths,
     # then PI samples that run the three-state filter for their estimates
     cfg = W.c3_uneven(n_samples=30, sample_id_offset=5000, model_nx=3, kin_lognorm_sigma=0.0,
-                      L_lo=20, L_hi=45)
+                      L_lo=20, L_hi=45, sqp_eps=EPS)
     phi, stats, ps, _ = gpu_run(cfg)
     ref = oracle_run(cfg)
     for f in ("kind", "N", "L", "n_ocp"):
         np.testing.assert_array_equal(ps[f], ref[f], err_msg=f)
     assert set(ps["N"].tolist()) == {10, 25, 50}
-    # the SQP stops at a scaled KKT residual of 1e-6, so in these start-up
-    # transients about half of the samples move by 1e-7..1e-6 between the
-    # oracle's own two gradient orders (bounded as in the c3 case)
-    good = compare_conditioned(cfg, phi, ps, ref, "3state classes")
-    assert good.sum() >= len(good) // 3
+    compare(phi, ps, ref, tag="3state classes")
 
 
 def test_three_state_trajectories_and_estimates():
@@ -471,7 +558,7 @@ def test_three_state_paired_line_search_is_the_serial_one():
 @pytest.mark.parametrize("over", [dict(n_samples=1), dict(L=0), dict(N=1), dict(sqp_max_iter=1),
                                   dict(n_samples=65, L=3)])
 def test_three_state_edge_cases(over):
-    cfg = W.c0_small_nmpc(**dict(dict(n_samples=5, L=5, model_nx=3), **over))
+    cfg = W.c0_small_nmpc(**dict(dict(n_samples=5, L=5, model_nx=3, sqp_eps=EPS), **over))
     phi, stats, ps, _ = gpu_run(cfg)
     ref = oracle_run(cfg)
     compare(phi, ps, ref, tag=f"3state edge {over}")
