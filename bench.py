@@ -45,6 +45,13 @@ def parse():
                     help="estimator / OCP model: 1 the paper's one-state model, 3 the three-state model")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain elementwise copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--plain-configs", default="c0,c1,c3,c4",
+                    help="configs of the adjoint-vs-plain comparison (subsets, equal eps)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the eps = 1e-8, Hessian-start and multiple-shooting side runs")
+    ap.add_argument("--nlp-form", type=int, default=0, choices=(0, 1),
+                    help="OCP discretisation: 0 single shooting, 1 the paper's multiple shooting")
+    ap.add_argument("--eps", type=float, default=0.0, help="SQP KKT tolerance (0: the recipe's)")
     return ap.parse_args()
 
 
@@ -78,13 +85,30 @@ def measured_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
+def host_cpu():
+    """Host CPU model name and logical CPU counts (all, and this process's)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
 def cpu_baseline(cfg, seconds):
     """The oracle, as it stands, on the host cores: NMPC closed loops of the
-    same workload, sample ids 0, 1, ... until about `seconds` of wall time."""
+    same workload, sample ids 0, 1, ... until about `seconds` of wall time.
+    Threads: the CPUs this process may use, at most 16 (one GPU's share of a
+    GPU host)."""
     import numpy as np
 
     import oracle
-    cores = min(16, len(os.sched_getaffinity(0)))  # one GPU's share of the host
+    model, n_all, n_aff = host_cpu()
+    cores = min(16, n_aff)
     n_nmpc = cfg["kind_split"] if cfg["kind_split"] >= 0 else cfg["n_samples"]
     done, wall, batch, start = 0, 0.0, cores, 0
     while wall < seconds and start < n_nmpc:
@@ -97,7 +121,29 @@ def cpu_baseline(cfg, seconds):
         log(f"cpu baseline: {done} samples, {wall:.1f} s")
     return dict(value=done / wall, unit="NMPC closed-loop sims/s", cores=cores, kind="oracle",
                 sample=f"NMPC sample ids 0..{done - 1} of the same workload ({done} closed loops, "
-                       f"{wall:.1f} s wall on {cores} threads)")
+                       f"{wall:.1f} s wall on {cores} threads; linear in the sample count, the "
+                       f"samples being independent)",
+                host_cpu_model=model, host_logical_cpus=n_all, cpus_available=n_aff)
+
+
+def describe(cfg, name):
+    """The workload in words, with the per-sample draws where there are any."""
+    N = ("N~U{" + ",".join(str(v) for v in cfg["horizon_choices"]) + "}"
+         if cfg["horizon_choices"] else f"N={cfg['N']}")
+    L = (f"L~U{{{cfg['L_lo']}..{cfg['L_hi']}}}" if cfg["L_lo"] < cfg["L_hi"] else f"L={cfg['L']}")
+    extra = []
+    if cfg["kin_lognorm_sigma"] > 0:
+        extra.append(f"plant kinetics x lognormal(sigma {cfg['kin_lognorm_sigma']})")
+    if cfg["sp_step_rel"] != 0:
+        extra.append(f"setpoint step +-{cfg['sp_step_rel']:.0%} at U{{{cfg['sp_step_lo']}.."
+                     f"{cfg['sp_step_hi']}}}")
+    if cfg.get("nlp_form", 0) == 1:
+        extra.append("multiple-shooting NLP")
+    if cfg.get("model_nx", 1) == 3:
+        extra.append("three-state estimator and OCP model")
+    return (f"{name}: {N}, {L}, Ns={cfg['Ns']}, Nc={cfg['Nc']}, seed={cfg['seed']}, "
+            f"SQP eps={cfg['sqp_eps']}, {'adjoint' if cfg['grad_mode'] == 1 else 'forward-sensitivity'}"
+            f" gradient" + "".join(", " + e for e in extra))
 
 
 def main():
@@ -118,7 +164,9 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: {n * 8} bytes read and written")
         del a, b
-    cfg = workloads.CONFIGS[args.config](model_nx=args.model_nx)
+    cfg = workloads.CONFIGS[args.config](model_nx=args.model_nx, nlp_form=args.nlp_form)
+    if args.eps > 0:
+        cfg["sqp_eps"] = args.eps
     if args.samples:
         cfg["n_samples"] = args.samples
         if cfg["kind_split"] >= 0:
@@ -159,16 +207,24 @@ def main():
     nmpc_flops = stats["flops_by_kind"][0]
     nmpc_ms = ms_kernels[0]
     roofline = None
-    if n_nmpc and nmpc_ms > 0:
+    # a chunked run's event spans mix the NMPC and PI kernels (ms[1] = -1):
+    # no per-kernel rate is derived from them
+    per_kernel = ms_kernels[1] >= 0
+    if n_nmpc and nmpc_ms > 0 and per_kernel:
         achieved = nmpc_flops / (nmpc_ms / 1000.0) / 1e12
+        standard = (args.config == "c1" and not args.samples and args.model_nx == 1
+                    and args.nlp_form == 0 and args.eps == 0)
+        traffic = measured_traffic() if standard else None
         roofline = dict(bound="alu", achieved=round(achieved, 4),
                         peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
                         frac=round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5),
-                        traffic=measured_traffic()
-                        if args.config == "c1" and not args.samples and args.model_nx == 1 else None)
+                        traffic=traffic)
+        if traffic:
+            # what the committed counters show besides the algorithmic rate
+            roofline["hbm_frac_measured"] = round(traffic / (nmpc_ms / 1000.0) / (HBM_PEAK_GBS * 1e9), 4)
     camp_flops = stats["flops_algorithmic"]
     pi_grad = None
-    if cfg.get("want_grad") and n_pi:
+    if cfg.get("want_grad") and n_pi and per_kernel:
         # the PI reverse pass (checkpointed adjoint through the closed loop)
         # after the timed forward step: d mean Phi / d(Kc, tau_i)
         torch.cuda.synchronize()
@@ -186,9 +242,20 @@ def main():
     camp.close()
 
     plain = None
-    if not args.no_plain and n_nmpc and args.model_nx == 1:
-        plain = adjoint_vs_plain(cfg, args.plain_samples)
-        log("adjoint vs plain done")
+    if not args.no_plain and n_nmpc and args.model_nx == 1 and args.nlp_form == 0:
+        plain = {}
+        for name in [c for c in args.plain_configs.split(",") if c]:
+            n = {"c0": 64, "c1": args.plain_samples, "c3": 2000, "c4": 5000}.get(name, 2000)
+            pc = workloads.CONFIGS[name]()
+            if args.eps > 0:
+                pc["sqp_eps"] = args.eps
+            plain[name] = adjoint_vs_plain(pc, n)
+            log(f"adjoint vs plain {name} done")
+
+    extras = None
+    if not args.no_extras and args.config == "c1" and not args.samples and args.model_nx == 1 \
+            and args.nlp_form == 0 and args.eps == 0:
+        extras = side_runs(cfg)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, args.cpu_seconds)
     scaling = cu_scaling(cfg) if args.cu_scaling else None
@@ -201,10 +268,8 @@ def main():
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{args.config}: {S} samples ({n_nmpc} NMPC N={cfg['N']} + {n_pi} PI), "
-                               f"L={cfg['L']}, Ns={cfg['Ns']}, Nc={cfg['Nc']}, seed={cfg['seed']}, "
-                               f"SQP eps={cfg['sqp_eps']}, adjoint gradient"
-                               + (", three-state estimator and OCP model" if args.model_nx == 3 else ""),
+        "config": {"workload": f"{S} samples ({n_nmpc} NMPC + {n_pi} PI), "
+                               + describe(cfg, args.config),
                    "samples": S, "nmpc_samples": n_nmpc, "pi_samples": n_pi},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -221,6 +286,7 @@ def main():
         "cu_scaling": scaling,
         "pi_gradient": pi_grad,
         "adjoint_vs_plain": plain,
+        "side_runs": extras,
         "algorithmic_gflop_per_step": round(camp_flops / 1e9, 3),
     }
     print(json.dumps(out))
@@ -256,6 +322,75 @@ def cu_scaling(cfg, samples=32768, L=20, spw=32):
         r["speedup"] = round(r["sims_per_s"] / r0, 3)
         r["efficiency"] = round(r["speedup"] / (r["cus"] / k0), 3)
     return dict(samples=samples, intervals=L, samples_per_wave=spw, rows=rows)
+
+
+def nmpc_subset_run(cfg, n, stride=1, **over):
+    """One timed run of n NMPC sample ids (0, stride, 2 stride, ...) of the
+    workload; returns rate, kernel time and the OCP statistics."""
+    import numpy as np
+    import torch
+
+    from paper_2212_02197_amd import binding
+    n_nm = cfg["kind_split"] if cfg["kind_split"] >= 0 else cfg["n_samples"]
+    ids = np.arange(0, n_nm, stride, dtype=np.int64)[:n]
+    c = dict(cfg, n_samples=len(ids), sample_ids=ids, kind_split=-1, default_kind=0,
+             noise_mod=cfg["noise_mod"], **over)
+    camp = binding.Campaign(c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    camp.run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    phi, st = camp.costs()
+    tot = st["totals"]
+    out = dict(samples=len(ids), id_stride=stride, sims_per_s=round(len(ids) / dt, 3),
+               nmpc_kernel_ms=round(camp.kernel_ms()[0], 3), ocp_total=tot["n_ocp"],
+               ocp_failed=tot["n_ocp_fail"],
+               sqp_iter_per_ocp=round(tot["sqp_iter"] / max(1, tot["n_ocp"]), 3),
+               mean_phi=st["mean"][0])
+    camp.close()
+    return out, phi
+
+
+def side_runs(cfg):
+    """Paper-scale side measurements: the whole campaign's NMPC half at
+    eps = 1e-8; the paper's W^[0] = I at every OCP with single shooting and
+    with the paper's multiple-shooting NLP, on strided NMPC subsets beside
+    the default single shooting with the shifted Hessian."""
+    import numpy as np
+    import torch
+
+    from paper_2212_02197_amd import binding
+    res = {}
+    c8 = dict(cfg, sqp_eps=1e-8)
+    camp = binding.Campaign(c8)
+    camp.run()
+    camp.costs()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    camp.run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _, st = camp.costs()
+    tot = st["totals"]
+    res["eps_1e-8"] = dict(nmpc_sims_per_s=round(st["count"][0] / dt, 3), ms_per_step=round(dt * 1e3, 3),
+                           nmpc_kernel_ms=round(camp.kernel_ms()[0], 3), ocp_total=tot["n_ocp"],
+                           ocp_failed=tot["n_ocp_fail"],
+                           sqp_iter_per_ocp=round(tot["sqp_iter"] / max(1, tot["n_ocp"]), 3))
+    camp.close()
+    log(f"eps 1e-8: {res['eps_1e-8']}")
+    n, stride = 1024, 29
+    base, phi0 = nmpc_subset_run(cfg, n, stride)
+    lit, phi1 = nmpc_subset_run(cfg, n, stride, hess_warm=0)
+    ms, phi2 = nmpc_subset_run(cfg, n, stride, nlp_form=1)
+    for r, ph in ((lit, phi1), (ms, phi2)):
+        r["max_rel_phi_diff_vs_default"] = float(np.max(np.abs(ph - phi0) / phi0))
+    res["hessian_start"] = dict(
+        single_shooting_shifted_W=base, single_shooting_W0_identity=lit,
+        multiple_shooting_W0_identity=ms,
+        paper_table_I="424 of 18,000,000 OCPs (0.0024 %) reach the 100-iteration cap")
+    log(f"hessian start: {res['hessian_start']}")
+    return res
 
 
 def adjoint_vs_plain(cfg, n):

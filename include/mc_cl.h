@@ -172,6 +172,26 @@ typedef struct {
     const uint8_t *kind;
     const int32_t *horizon;
     const int32_t *lengths;
+    /* Discretisation of the NMPC's OCP: 0 single shooting (the inputs are
+     * the decision variables; the settings above); 1 direct multiple
+     * shooting, eq. (OCP_NLP), the paper's own NLP: states and inputs are
+     * decision variables, the structured QP eq. (QP-subproblem) is solved by
+     * a Riccati-recursion primal-dual interior point, the line search uses
+     * Powell's l1 merit, the Hessian is the block damped BFGS from W^[0] = I
+     * at every OCP (hess_warm, qp_solver, grad_mode and samples_per_wave do
+     * not apply; 64 samples per wavefront).  1 needs model_nx = 1
+     * (EUNSUPPORTED otherwise) and umin < umax (EINVAL).                    */
+    int32_t nlp_form;
+    /* Optional caller-owned device workspace (NULL: the library allocates).
+     * When given, every device buffer of the context is carved from it, in
+     * order, 256-byte aligned; workspace_size must be at least what
+     * mc_cl_workspace_size reports for the same parameters (ENOMEM
+     * otherwise), the pointer 256-byte aligned (EINVAL otherwise).  It must
+     * stay valid until mc_cl_destroy; the library never frees it.
+     * mc_cl_tune may need more (its trial shapes grow the workspaces):
+     * ENOMEM when the rest does not hold them.                              */
+    void *workspace;
+    size_t workspace_size;
 } mc_cl_params;
 
 /* Optional outputs of mc_cl_run; every pointer may be NULL.  All are device
@@ -286,6 +306,12 @@ typedef struct {
     float grad_ms[MC_CL_TUNE_NCK];        /* trial time per candidate C      */
 } mc_cl_tune_result;
 int mc_cl_tune(mc_cl_ctx *c, void *hip_stream, int32_t trial_intervals, mc_cl_tune_result *r);
+
+/* Device bytes mc_cl_create needs for these parameters (their workspace
+ * fields are ignored), for a caller-passed workspace.  Plans the campaign
+ * on the current device as mc_cl_create does (allocating and releasing its
+ * buffers).  Errors as mc_cl_create.                                        */
+int mc_cl_workspace_size(const mc_cl_params *p, size_t *bytes);
 
 /* A HIP stream on the current device whose kernels run on its first n_cu
  * compute units only (a CU-masked stream; n_cu <= 0 or >= the device's

@@ -54,7 +54,8 @@ class Params(C.Structure):
         ("qp_solver", C.c_int32), ("chunk_samples", C.c_int32),
         ("cu_limit", C.c_int32), ("model_nx", C.c_int32),
         ("sample_ids", C.c_void_p), ("kind", C.c_void_p), ("horizon", C.c_void_p),
-        ("lengths", C.c_void_p),
+        ("lengths", C.c_void_p), ("nlp_form", C.c_int32),
+        ("workspace", C.c_void_p), ("workspace_size", C.c_size_t),
     ]
 
 
@@ -82,7 +83,7 @@ class TuneResult(C.Structure):
 
 EXPORTS = ["mc_cl_create", "mc_cl_run", "mc_cl_costs", "mc_cl_grad", "mc_cl_destroy",
            "mc_cl_strerror", "mc_cl_abi_version", "mc_cl_kernel_ms", "mc_cl_plan",
-           "mc_cl_tune", "mc_cl_stream_create", "mc_cl_stream_destroy"]
+           "mc_cl_tune", "mc_cl_stream_create", "mc_cl_stream_destroy", "mc_cl_workspace_size"]
 
 _lib = None
 
@@ -123,6 +124,8 @@ def lib():
         L.mc_cl_stream_create.argtypes = [C.c_int32, C.POINTER(vp)]
         L.mc_cl_stream_destroy.restype = C.c_int
         L.mc_cl_stream_destroy.argtypes = [vp]
+        L.mc_cl_workspace_size.restype = C.c_int
+        L.mc_cl_workspace_size.argtypes = [C.POINTER(Params), C.POINTER(C.c_size_t)]
         _lib = L
     return _lib
 
@@ -173,6 +176,7 @@ def params(cfg: dict, arrays: dict = None) -> Params:
     p.chunk_samples = cfg.get("chunk_samples", 0)
     p.cu_limit = cfg.get("cu_limit", 0)
     p.model_nx = cfg.get("model_nx", 1)
+    p.nlp_form = cfg.get("nlp_form", 0)
     for a in range(3):
         p.sigma[a] = cfg["sigma"][a]
     sp_i, sp_z = cfg["sp_i"], cfg["sp_z"]
@@ -195,13 +199,20 @@ class Campaign:
     """One mc_cl context: create on the current device, run on a torch stream,
     read costs, statistics and the PI gradient."""
 
-    def __init__(self, cfg: dict):
+    def __init__(self, cfg: dict, workspace=None):
+        """workspace: optional torch uint8 tensor on the device, at least
+        workspace_size(cfg) bytes, that the context's buffers are carved
+        from (kept referenced by the campaign)."""
         import torch
         self.torch = torch
         self.cfg = dict(cfg)
         self.S = int(cfg["n_samples"])
         arrays = per_sample_arrays(self.cfg)
         self.p = params(self.cfg, arrays)
+        self.workspace = workspace
+        if workspace is not None:
+            self.p.workspace = workspace.data_ptr()
+            self.p.workspace_size = workspace.numel() * workspace.element_size()
         h = C.c_void_p()
         _check(lib().mc_cl_create(C.byref(self.p), C.byref(h)), "mc_cl_create")
         self.h = h
@@ -305,6 +316,15 @@ class Campaign:
         n = lib().mc_cl_plan(self.h, buf, 3)
         return [dict(nmax=buf[5 * k], count=buf[5 * k + 1], spw=buf[5 * k + 2],
                      groups=buf[5 * k + 3], slots=buf[5 * k + 4]) for k in range(n)]
+
+
+def workspace_size(cfg: dict) -> int:
+    """mc_cl_workspace_size: device bytes a campaign of cfg needs."""
+    arrays = per_sample_arrays(cfg)
+    p = params(cfg, arrays)
+    b = C.c_size_t()
+    _check(lib().mc_cl_workspace_size(C.byref(p), C.byref(b)), "mc_cl_workspace_size")
+    return int(b.value)
 
 
 def _pi_closed_loop_function():

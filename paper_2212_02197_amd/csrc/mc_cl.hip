@@ -17,6 +17,7 @@
 
 #include "mc_cl.h"
 #include "mc_kernels.hpp"
+#include "mc_ms.hpp"
 
 using namespace mccl;
 
@@ -89,6 +90,22 @@ hipError_t launch_nmpc(const DevParams& dp, const NmpcWork& wk, const Outs& o, i
     return hipGetLastError();
 }
 
+template <int NMAX>
+hipError_t launch_ms(const DevParams& dp, const NmpcWork& wk, const Outs& o, int slots,
+                     hipStream_t st) {
+    MsWork mw{wk.pos, wk.n_pos, wk.n_groups, wk.queue, wk.qhi, wk.tiles, wk.tile_stride};
+    hipLaunchKernelGGL((nmpc_ms_kernel<NMAX>), dim3(slots), dim3(64), 0, st, dp, mw, o);
+    return hipGetLastError();
+}
+
+template <int NMAX>
+int ms_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, nmpc_ms_kernel<NMAX>, 64, 0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
 template <int NMAX, int GMODE, int NX>
 int max_blocks_per_cu() {
     int nb = 0;
@@ -100,7 +117,12 @@ int max_blocks_per_cu() {
 
 // Kernel variants: horizon class NMAX x gradient mode x model states; the
 // three-state model runs with the adjoint gradient only (validated).
-int blocks_per_cu(int nmax, int gmode, int nx) {
+int blocks_per_cu(int nmax, int gmode, int nx, int nlp_form = 0) {
+    if (nlp_form == 1) {
+        if (nmax == 16) return ms_blocks_per_cu<16>();
+        if (nmax == 32) return ms_blocks_per_cu<32>();
+        return ms_blocks_per_cu<64>();
+    }
     if (nx == 3) {
         if (nmax == 16) return max_blocks_per_cu<16, 1, 3>();
         if (nmax == 32) return max_blocks_per_cu<32, 1, 3>();
@@ -118,6 +140,11 @@ int blocks_per_cu(int nmax, int gmode, int nx) {
 
 hipError_t dispatch_nmpc(int nmax, int gmode, int nx, const DevParams& dp, const NmpcWork& wk,
                          const Outs& o, int slots, hipStream_t st) {
+    if (dp.nlp_form == 1) {
+        if (nmax == 16) return launch_ms<16>(dp, wk, o, slots, st);
+        if (nmax == 32) return launch_ms<32>(dp, wk, o, slots, st);
+        return launch_ms<64>(dp, wk, o, slots, st);
+    }
     if (nx == 3) {
         if (nmax == 16) return launch_nmpc<16, 1, 3>(dp, wk, o, slots, st);
         if (nmax == 32) return launch_nmpc<32, 1, 3>(dp, wk, o, slots, st);
@@ -178,25 +205,45 @@ struct mc_cl_ctx {
     bool ran = false;
     bool grad_ran = false;
     size_t bytes = 0;
+    size_t bytes_aligned = 0;   // the same allocations rounded up to 256 bytes each
     std::vector<void*> allocs;
 
     std::vector<size_t> alloc_bytes;
+    // caller-passed workspace (mc_cl_params.workspace): the allocations are
+    // carved from it in order, 256-byte aligned, and never freed
+    unsigned char* ws_base = nullptr;
+    size_t ws_size = 0, ws_used = 0;
 
     template <class T>
     int alloc(T** p, size_t n) {
         *p = nullptr;
         if (n == 0) return MC_CL_OK;
+        const size_t b = (n * sizeof(T) + 255) & ~(size_t)255;
+        if (ws_base) {
+            if (ws_used + b > ws_size) {
+                g_hip_error = "caller workspace too small";
+                return MC_CL_ENOMEM;
+            }
+            *p = (T*)(ws_base + ws_used);
+            ws_used += b;
+            bytes += b;
+            bytes_aligned += b;
+            return MC_CL_OK;
+        }
         void* v = nullptr;
         HIPCHK(hipMalloc(&v, n * sizeof(T)));
         allocs.push_back(v);
         alloc_bytes.push_back(n * sizeof(T));
         bytes += n * sizeof(T);
+        bytes_aligned += b;
         *p = (T*)v;
         return MC_CL_OK;
     }
-    // Free *p (if the context owns it) and allocate n elements instead.
+    // Free *p (if the context owns it) and allocate n elements instead (in a
+    // caller workspace: a new piece; the old one stays unused).
     template <class T>
     int realloc_dev(T** p, size_t n) {
+        if (ws_base) return alloc(p, n);
         for (size_t k = 0; k < allocs.size(); ++k) {
             if (allocs[k] == (void*)*p && *p) {
                 HIPCHK(hipFree(allocs[k]));
@@ -280,6 +327,11 @@ static int validate(const mc_cl_params* p) {
     if (p->chunk_samples < 0 || p->cu_limit < 0) return MC_CL_EINVAL;
     if (p->model_nx != 1 && p->model_nx != 3) return MC_CL_EINVAL;
     if (p->model_nx == 3 && p->grad_mode != 1) return MC_CL_EUNSUPPORTED;
+    if (p->nlp_form != 0 && p->nlp_form != 1) return MC_CL_EINVAL;
+    if (p->nlp_form == 1 && !(p->umin < p->umax)) return MC_CL_EINVAL;
+    if (p->nlp_form == 1 && p->model_nx != 1) return MC_CL_EUNSUPPORTED;
+    if (p->workspace && (p->workspace_size == 0 || ((uintptr_t)p->workspace & 255u) != 0))
+        return MC_CL_EINVAL;
     if (!p->sample_ids &&
         (p->sample_id_offset < 0 || p->sample_id_offset + p->n_samples > (int64_t)UINT32_MAX))
         return MC_CL_EINVAL;
@@ -296,12 +348,15 @@ static int validate(const mc_cl_params* p) {
 // Launch shape of an NMPC class for `spw` samples per wavefront; grows the
 // class's wave-slot workspaces when the shape needs more of them.
 static int plan_class(mc_cl_ctx* c, NmpcClass& nc, int spw) {
+    const bool ms = c->prm.nlp_form == 1;
+    if (ms) spw = 64;   // one sample per lane, every lane
     nc.spw = spw;
     nc.groups = (int)((nc.count + spw - 1) / spw);
     nc.slots = std::min(nc.groups, nc.slots_full);
-    nc.tile_stride = (int64_t)V_COUNT * nc.nmax * 64;
-    nc.xs_stride = (int64_t)(c->prm.model_nx == 3 ? rec_width<3>() : rec_width<1>()) * nc.nmax * 64;
-    nc.w_stride = (int64_t)spw * nc.nmax * nc.nmax;
+    // multiple shooting: the stage arrays of the slot take the tile buffer
+    nc.tile_stride = (int64_t)(ms ? (int)M_COUNT : (int)V_COUNT) * nc.nmax * 64;
+    nc.xs_stride = ms ? 0 : (int64_t)(c->prm.model_nx == 3 ? rec_width<3>() : rec_width<1>()) * nc.nmax * 64;
+    nc.w_stride = ms ? 0 : (int64_t)spw * nc.nmax * nc.nmax;
     const size_t nt = (size_t)nc.slots * nc.tile_stride;
     const size_t nx = (size_t)nc.slots * nc.xs_stride;
     const size_t nw = (size_t)nc.slots * nc.w_stride;
@@ -329,7 +384,7 @@ static int size_ckpt(mc_cl_ctx* c, int C) {
     const int64_t nseg = std::max<int64_t>((c->Lmax + C - 1) / C, 1);
     int rc;
     if ((rc = c->realloc_dev(&c->d_ck, (size_t)nseg * 4 * c->n_pi)) ||
-        (rc = c->realloc_dev(&c->d_tape, (size_t)C * c->prm.Ns * 6 * c->n_pi)) ||
+        (rc = c->realloc_dev(&c->d_tape, (size_t)C * c->prm.Ns * 3 * c->n_pi)) ||
         (rc = c->realloc_dev(&c->d_ivtape, (size_t)C * 5 * c->n_pi)))
         return rc;
     c->ckC = C;
@@ -462,6 +517,7 @@ static DevParams to_dev(const mc_cl_params& p) {
     d.kind_ov = nullptr;
     d.N_ov = nullptr;
     d.L_ov = nullptr;
+    d.nlp_form = p.nlp_form;
     return d;
 }
 
@@ -540,6 +596,11 @@ int mc_cl_create(const mc_cl_params* p, mc_cl_ctx** out) {
     c->prm = *p;
     c->dp = to_dev(*p);
     c->S = p->n_samples;
+    if (p->workspace) {
+        c->ws_base = (unsigned char*)p->workspace;
+        c->ws_size = p->workspace_size;
+    }
+    c->prm.workspace = nullptr;   // the context keeps its own record of it
     if (hipGetDevice(&c->device) != hipSuccess) return fail(MC_CL_EHIP);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return fail(MC_CL_EHIP);
@@ -620,7 +681,7 @@ int mc_cl_create(const mc_cl_params* p, mc_cl_ctx** out) {
         nc.nmax = nmaxs[k];
         nc.count = (int64_t)v.size();
         c->n_nmpc += nc.count;
-        const int bpc = blocks_per_cu(nc.nmax, gmode, p->model_nx);
+        const int bpc = blocks_per_cu(nc.nmax, gmode, p->model_nx, p->nlp_form);
         nc.slots_full = bpc * c->n_cu;
         int nmax_in_class = 1;
         for (int64_t q : v) nmax_in_class = std::max(nmax_in_class, Nv[q]);
@@ -823,6 +884,12 @@ int mc_cl_tune(mc_cl_ctx* c, void* hip_stream, int32_t trial_intervals, mc_cl_tu
     for (size_t k = 0; k < c->classes.size() && rc == MC_CL_OK; ++k) {
         NmpcClass& nc = c->classes[k];
         r->nmax[k] = nc.nmax;
+        if (c->prm.nlp_form == 1) {
+            // one sample per lane: nothing to choose
+            for (int j = 0; j < MC_CL_TUNE_NSPW; ++j) r->nmpc_ms[k][j] = -1.0f;
+            r->spw[k] = nc.spw;
+            continue;
+        }
         float best = INFINITY;
         int bspw = nc.spw;
         for (int j = 0; j < MC_CL_TUNE_NSPW && rc == MC_CL_OK; ++j) {
@@ -908,6 +975,20 @@ int mc_cl_stream_create(int32_t n_cu, void** stream) {
 int mc_cl_stream_destroy(void* stream) {
     if (!stream) return MC_CL_EINVAL;
     HIPCHK(hipStreamDestroy((hipStream_t)stream));
+    return MC_CL_OK;
+}
+
+int mc_cl_workspace_size(const mc_cl_params* p, size_t* bytes) {
+    if (!p || !bytes) return MC_CL_EINVAL;
+    *bytes = 0;
+    mc_cl_params q = *p;
+    q.workspace = nullptr;
+    q.workspace_size = 0;
+    mc_cl_ctx* c = nullptr;
+    const int rc = mc_cl_create(&q, &c);
+    if (rc != MC_CL_OK) return rc;
+    *bytes = c->bytes_aligned;
+    mc_cl_destroy(c);
     return MC_CL_OK;
 }
 

@@ -61,6 +61,7 @@ struct DevParams {
     const uint8_t* kind_ov;
     const int32_t* N_ov;
     const int32_t* L_ov;
+    int nlp_form;        // OCP discretisation: 0 single shooting, 1 multiple shooting
 };
 
 // Noise streams: the counter's last word.

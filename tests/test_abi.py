@@ -108,6 +108,30 @@ def test_invalid_parameters_are_rejected_before_any_device_call(lib, over):
     assert _create(workloads.c0_small_nmpc(), **over) == -1
 
 
+def test_caller_workspace_is_checked_before_any_device_call(lib):
+    from paper_2212_02197_amd import workloads
+    cfg = workloads.c0_small_nmpc(n_samples=4)
+    p = binding.params(cfg)
+    h = C.c_void_p()
+    p.workspace = 0x1000 + 8          # not 256-byte aligned
+    p.workspace_size = 1 << 20
+    assert lib.mc_cl_create(C.byref(p), C.byref(h)) == -1
+    p.workspace = 0x1000
+    p.workspace_size = 0
+    assert lib.mc_cl_create(C.byref(p), C.byref(h)) == -1
+    b = C.c_size_t()
+    assert lib.mc_cl_workspace_size(None, C.byref(b)) == -1
+
+
+def test_multiple_shooting_parameters_are_checked(lib):
+    from paper_2212_02197_amd import workloads
+    unsupported = [k for k, v in binding.STATUS.items() if v == "MC_CL_EUNSUPPORTED"][0]
+    cfg = workloads.c0_small_nmpc()
+    assert _create(cfg, nlp_form=2) == -1
+    assert _create(cfg, nlp_form=1, umin=5.0, umax=5.0) == -1
+    assert _create(cfg, nlp_form=1, model_nx=3) == unsupported
+
+
 def test_three_state_model_needs_the_adjoint_gradient(lib):
     from paper_2212_02197_amd import workloads
     unsupported = [k for k, v in binding.STATUS.items() if v == "MC_CL_EUNSUPPORTED"][0]
