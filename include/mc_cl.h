@@ -313,6 +313,30 @@ int mc_cl_tune(mc_cl_ctx *c, void *hip_stream, int32_t trial_intervals, mc_cl_tu
  * buffers).  Errors as mc_cl_create.                                        */
 int mc_cl_workspace_size(const mc_cl_params *p, size_t *bytes);
 
+/* Allocation-free run, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Runs the campaign `p` describes on hip_stream with the same
+ * kernels as mc_cl_create + mc_cl_run and the same results (the launch shape
+ * differs; Phi, the counters and the hashes do not depend on it), but
+ * allocates nothing: the per-sample lists, the work queues and the NMPC
+ * workspaces live in a library-owned device array of
+ * MC_CL_STATIC_SCRATCH_BYTES per device (taken when the library is loaded
+ * on the device, held until the process ends).
+ * Outputs: o->phi ([S], device) is required; o->counters and o->ashash are
+ * optional device outputs as for mc_cl_run; trajectories, want_grad,
+ * chunking, the per-sample arrays and nlp_form 1 are EUNSUPPORTED; the
+ * workspace fields are ignored.  No statistics are
+ * formed.  Synchronises hip_stream once (after planning), then returns with
+ * the campaign's kernels queued on it.
+ * EINVAL for invalid parameters or outputs, or when the campaign needs more
+ * than the array: about 96 bytes per sample (88 when the caller takes the
+ * counters, 80 with the hashes too) plus one wavefront slot of one sample
+ * (about 0.5 MB at N > 32).  Every call on a device shares that device's
+ * array and overwrites the last call's contents: calls that overlap on one
+ * device (two streams, two threads) race and must not be made.            */
+#define MC_CL_STATIC_SCRATCH_BYTES (64u << 20)
+int mc_cl_run_static(const mc_cl_params *p, void *hip_stream, const mc_cl_outputs *o);
+
 /* A HIP stream on the current device whose kernels run on its first n_cu
  * compute units only (a CU-masked stream; n_cu <= 0 or >= the device's
  * count: all), for throughput against compute units (the GPU analogue of

@@ -83,7 +83,9 @@ class TuneResult(C.Structure):
 
 EXPORTS = ["mc_cl_create", "mc_cl_run", "mc_cl_costs", "mc_cl_grad", "mc_cl_destroy",
            "mc_cl_strerror", "mc_cl_abi_version", "mc_cl_kernel_ms", "mc_cl_plan",
-           "mc_cl_tune", "mc_cl_stream_create", "mc_cl_stream_destroy", "mc_cl_workspace_size"]
+           "mc_cl_tune", "mc_cl_stream_create", "mc_cl_stream_destroy", "mc_cl_workspace_size",
+           "mc_cl_run_static"]
+STATIC_SCRATCH_BYTES = 64 << 20
 
 _lib = None
 
@@ -126,6 +128,8 @@ def lib():
         L.mc_cl_stream_destroy.argtypes = [vp]
         L.mc_cl_workspace_size.restype = C.c_int
         L.mc_cl_workspace_size.argtypes = [C.POINTER(Params), C.POINTER(C.c_size_t)]
+        L.mc_cl_run_static.restype = C.c_int
+        L.mc_cl_run_static.argtypes = [C.POINTER(Params), vp, C.POINTER(Outputs)]
         _lib = L
     return _lib
 
@@ -325,6 +329,21 @@ def workspace_size(cfg: dict) -> int:
     b = C.c_size_t()
     _check(lib().mc_cl_workspace_size(C.byref(p), C.byref(b)), "mc_cl_workspace_size")
     return int(b.value)
+
+
+def run_static(cfg: dict, phi, counters=None, ashash=None, stream=None):
+    """mc_cl_run_static: the campaign with no device allocation by the
+    library, into caller tensors phi ([S] float64), counters ([NCNT, S]
+    int32) and ashash ([S] int64) on the current device (the last two may be
+    None).  Queued on `stream` (default: the current stream)."""
+    import torch
+    arrays = per_sample_arrays(cfg)
+    p = params(cfg, arrays)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    o = Outputs(phi.data_ptr(), None if counters is None else counters.data_ptr(),
+                None if ashash is None else ashash.data_ptr(), None, None, None)
+    _check(lib().mc_cl_run_static(C.byref(p), C.c_void_p(st.cuda_stream), C.byref(o)),
+           "mc_cl_run_static")
 
 
 def _pi_closed_loop_function():

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -161,6 +162,78 @@ hipError_t dispatch_nmpc(int nmax, int gmode, int nx, const DevParams& dp, const
 }
 
 bool is_finite(double v) { return std::isfinite(v); }
+
+// Allocation-free runs (mc_cl_run_static): the device memory they use beyond
+// the caller's inputs and outputs lives in this file-scope array, one copy
+// per device, held until the process ends.  Host code never passes the
+// array's name to a kernel: it takes the device address from
+// hipGetSymbolAddress once per device (scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[MC_CL_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up on the
+// first call on that device).
+int scratch_ptr(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= kMaxDevices) return MC_CL_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) {
+            g_hip_error = "hipGetSymbolAddress returned a null address for the scratch array";
+            return MC_CL_EHIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = (unsigned char*)g_scratch_ptr[dev];
+    return MC_CL_OK;
+}
+
+// Per-sample lists of an allocation-free run, built on the device by one
+// block: positions of the NMPC samples of each horizon class (0, 1, 2:
+// NMAX 16, 32, 64) and of the PI samples (3), each list in column order,
+// stored one after another in `pos`; counts[0..3] the list lengths.
+__global__ __launch_bounds__(1024) void bucket_kernel(const int32_t* kind, const int32_t* N,
+                                                      int64_t S, int64_t* pos, int* counts) {
+    __shared__ int64_t part[4][1024];
+    __shared__ int64_t base[4];
+    const int t = threadIdx.x;
+    const int64_t lo = S * t / 1024, hi = S * (t + 1) / 1024;
+    int64_t c[4] = {0, 0, 0, 0};
+    auto cls = [&](int64_t s) -> int {
+        if (kind[s] == 1) return 3;
+        return N[s] <= 16 ? 0 : (N[s] <= 32 ? 1 : 2);
+    };
+    for (int64_t s = lo; s < hi; ++s) c[cls(s)]++;
+    for (int k = 0; k < 4; ++k) part[k][t] = c[k];
+    __syncthreads();
+    if (t < 4) {
+        int64_t run = 0;
+        for (int j = 0; j < 1024; ++j) {
+            const int64_t v = part[t][j];
+            part[t][j] = run;
+            run += v;
+        }
+        base[t] = run;   // class total, turned into list offsets below
+    }
+    __syncthreads();
+    if (t == 0) {
+        int64_t off = 0;
+        for (int k = 0; k < 4; ++k) {
+            counts[k] = (int)base[k];
+            const int64_t n = base[k];
+            base[k] = off;
+            off += n;
+        }
+    }
+    __syncthreads();
+    int64_t w[4];
+    for (int k = 0; k < 4; ++k) w[k] = base[k] + part[k][t];
+    for (int64_t s = lo; s < hi; ++s) pos[w[cls(s)]++] = s;
+}
 
 }  // namespace
 
@@ -989,6 +1062,123 @@ int mc_cl_workspace_size(const mc_cl_params* p, size_t* bytes) {
     if (rc != MC_CL_OK) return rc;
     *bytes = c->bytes_aligned;
     mc_cl_destroy(c);
+    return MC_CL_OK;
+}
+
+int mc_cl_run_static(const mc_cl_params* p, void* hip_stream, const mc_cl_outputs* o) {
+    if (!o || !o->phi) return MC_CL_EINVAL;
+    int rc = validate(p);
+    if (rc != MC_CL_OK) return rc;
+    if (o->traj_z || o->traj_u || o->traj_xhat || p->want_grad || p->chunk_samples > 0 ||
+        p->sample_ids || p->kind || p->horizon || p->lengths || p->nlp_form != 0)
+        return MC_CL_EUNSUPPORTED;
+    const int64_t S = p->n_samples;
+    // scratch layout (256-byte aligned pieces): per-sample kind, N, L,
+    // positions, work, counters and hashes (the last two only when the
+    // caller does not take them), queue counters, then the wavefront
+    // slots' NMPC workspaces
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t b_plan = 3 * al((size_t)S * 4);
+    const size_t b_pos = al((size_t)S * 8), b_fl = al((size_t)S * 8);
+    const size_t b_cnt = o->counters ? 0 : al((size_t)C_NCNT * S * 4);
+    const size_t b_hash = o->ashash ? 0 : al((size_t)S * 8);
+    const size_t b_ctl = 256;
+    const size_t fixed = b_plan + b_pos + b_fl + b_cnt + b_hash + b_ctl;
+    int nmax_hi = nmax_class(p->N);
+    for (int j = 0; j < p->n_horizon_choices; ++j)
+        nmax_hi = std::max(nmax_hi, nmax_class(p->horizon_choices[j]));
+    const int rw = p->model_nx == 3 ? rec_width<3>() : rec_width<1>();
+    auto slot_bytes = [&](int nmax, int spw) {
+        return al((size_t)V_COUNT * nmax * 64 * 8) + al((size_t)rw * nmax * 64 * 8) +
+               al((size_t)spw * nmax * nmax * 8);
+    };
+    // the campaign must fit with at least one wavefront slot of one sample
+    if (fixed + slot_bytes(nmax_hi, 1) > (size_t)MC_CL_STATIC_SCRATCH_BYTES) return MC_CL_EINVAL;
+
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    unsigned char* base = nullptr;
+    if ((rc = scratch_ptr(dev, &base)) != MC_CL_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    unsigned char* q = base;
+    auto take = [&](size_t b) { unsigned char* r = q; q += b; return r; };
+    int32_t* d_kind = (int32_t*)take(al((size_t)S * 4));
+    int32_t* d_N = (int32_t*)take(al((size_t)S * 4));
+    int32_t* d_L = (int32_t*)take(al((size_t)S * 4));
+    int64_t* d_pos = (int64_t*)take(b_pos);
+    double* d_flops = (double*)take(b_fl);
+    int32_t* d_cnt = o->counters ? o->counters : (int32_t*)take(b_cnt);
+    uint64_t* d_hash = o->ashash ? o->ashash : (uint64_t*)take(b_hash);
+    int* d_ctl = (int*)take(b_ctl);   // [0..3] queues, [4..7] list lengths
+    unsigned char* ws = q;
+    const size_t ws_bytes = (size_t)MC_CL_STATIC_SCRATCH_BYTES - (size_t)(q - base);
+
+    const DevParams dp = to_dev(*p);
+    hipLaunchKernelGGL(plan_kernel, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, st, dp, S,
+                       d_kind, d_N, d_L);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(bucket_kernel, dim3(1), dim3(1024), 0, st, d_kind, d_N, S, d_pos, d_ctl + 4);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, d_ctl, 4, 0);
+    HIPCHK(hipGetLastError());
+    int counts[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(counts, d_ctl + 4, sizeof(counts), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    int n_cu = prop.multiProcessorCount;
+    if (p->cu_limit > 0 && p->cu_limit < n_cu) n_cu = p->cu_limit;
+    const Outs out{o->phi, d_flops, d_cnt, d_hash, nullptr, nullptr, nullptr, S};
+    static const int nmaxs[3] = {16, 32, 64};
+    int64_t off = 0;
+    // horizon classes one after another on the stream, each using the whole
+    // workspace region for its wavefront slots
+    for (int k = 0; k < 3; ++k) {
+        const int64_t count = counts[k];
+        if (count == 0) continue;
+        const int nmax = nmaxs[k];
+        const int slots_full = blocks_per_cu(nmax, p->grad_mode, p->model_nx) * n_cu;
+        int nmax_in_class = 1;
+        if (p->n_horizon_choices > 0) {
+            for (int j = 0; j < p->n_horizon_choices; ++j)
+                if (nmax_class(p->horizon_choices[j]) == nmax)
+                    nmax_in_class = std::max(nmax_in_class, p->horizon_choices[j]);
+        } else {
+            nmax_in_class = p->N;
+        }
+        int spw = p->samples_per_wave > 0
+                      ? p->samples_per_wave
+                      : balanced_spw(count, choose_spw(count, nmax_in_class, slots_full), slots_full);
+        int64_t groups = (count + spw - 1) / spw;
+        int64_t slots = std::min<int64_t>(groups, slots_full);
+        slots = std::min<int64_t>(slots, (int64_t)(ws_bytes / slot_bytes(nmax, spw)));
+        while (slots < 1 && spw > 1) {
+            spw = std::max(1, spw / 2);
+            groups = (count + spw - 1) / spw;
+            slots = std::min<int64_t>(std::min<int64_t>(groups, slots_full),
+                                      (int64_t)(ws_bytes / slot_bytes(nmax, spw)));
+        }
+        if (slots < 1) return MC_CL_EINVAL;   // cannot happen after the size check above
+        const int64_t tile_stride = (int64_t)V_COUNT * nmax * 64;
+        const int64_t xs_stride = (int64_t)rw * nmax * 64;
+        const int64_t w_stride = (int64_t)spw * nmax * nmax;
+        // three regions; each rounded up is at most `slots` times its
+        // rounded per-slot size, so they fit in slots * slot_bytes
+        double* tiles = (double*)ws;
+        double* xs = (double*)(ws + al((size_t)slots * tile_stride * 8));
+        double* W = (double*)(ws + al((size_t)slots * tile_stride * 8) +
+                              al((size_t)slots * xs_stride * 8));
+        NmpcWork wk{d_pos + off, count, spw, (int)groups, d_ctl + k, nullptr, tiles, xs, W,
+                    tile_stride, xs_stride, w_stride};
+        HIPCHK(dispatch_nmpc(nmax, p->grad_mode, p->model_nx, dp, wk, out, (int)slots, st));
+        off += count;
+    }
+    if (counts[3] > 0) {
+        hipLaunchKernelGGL(pi_kernel, dim3((unsigned)((counts[3] + 63) / 64)), dim3(64), 0, st, dp,
+                           d_pos + off, (int64_t)counts[3], out, nullptr, nullptr, (int64_t)0);
+        HIPCHK(hipGetLastError());
+    }
     return MC_CL_OK;
 }
 

@@ -166,3 +166,29 @@ def test_stream_helpers_reject_null(lib):
     assert lib.mc_cl_stream_create(4, None) == -1
     assert lib.mc_cl_stream_destroy(None) == -1
 
+
+def test_static_run_rejects_before_any_device_call(lib):
+    # mc_cl_run_static checks its arguments and the campaign's size against
+    # the scratch array before it touches the device
+    from paper_2212_02197_amd import workloads
+    phi = (C.c_double * 4)()
+
+    def call(cfg, **o):
+        arrays = binding.per_sample_arrays(cfg)
+        p = binding.params(cfg, arrays)
+        out = binding.Outputs(C.cast(phi, C.c_void_p).value, None, None, None, None, None)
+        for k, v in o.items():
+            setattr(out, k, v)
+        return lib.mc_cl_run_static(C.byref(p), None, C.byref(out))
+
+    cfg = workloads.c0_small_nmpc(n_samples=4)
+    assert lib.mc_cl_run_static(C.byref(binding.params(cfg)), None, None) == -1
+    assert call(cfg, phi=None) == -1
+    assert call(dict(cfg, N=0)) == -1
+    assert call(cfg, traj_z=1234) == -5
+    assert call(dict(cfg, want_grad=1)) == -5
+    assert call(dict(cfg, chunk_samples=2)) == -5
+    assert call(dict(cfg, lengths=[1, 2, 3, 4])) == -5
+    # about 96 bytes per sample: a million samples exceed the 64 MiB array
+    assert binding.STATIC_SCRATCH_BYTES == 64 << 20
+    assert call(workloads.c4_mixed()) == -1
