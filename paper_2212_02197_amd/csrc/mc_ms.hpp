@@ -150,7 +150,7 @@ __device__ int ms_qp(const DevParams& p, const MsArr<NMAX>& a, int N, int& iters
     double gsc = 0.0;
     {
         double dx = 0.0;
-        #pragma unroll 1
+        #pragma unroll 4
         for (int k = 0; k < N; ++k) {
             const double lo = p.umin - a(M_U, k), hi = p.umax - a(M_U, k);
             const double dl = 1e-2 * (hi - lo);
@@ -176,7 +176,7 @@ __device__ int ms_qp(const DevParams& p, const MsArr<NMAX>& a, int N, int& iters
         double rxN = a(M_WXX, N - 1) * a(M_DX, N - 1) + a(M_FX, N - 1) + a(M_MU, N - 1);
         double pn = rxN;
         double rmax = fabs(rxN), wd = fabs(a(M_WXX, N - 1) * a(M_DX, N - 1)), comp = 0.0;
-        #pragma unroll 1
+        #pragma unroll 4
         for (int k = N - 1; k >= 0; --k) {
             const double A = a(M_A, k), B = a(M_B, k);
             const double du = a(M_DU, k), nl = a(M_NL, k), nu = a(M_NU, k), mu = a(M_MU, k);
@@ -220,7 +220,7 @@ __device__ int ms_qp(const DevParams& p, const MsArr<NMAX>& a, int N, int& iters
         double apr = 1.0, adr = 1.0;
         {
             double dx = 0.0;
-            #pragma unroll 1
+            #pragma unroll 4
             for (int k = 0; k < N; ++k) {
                 const double dua = (k >= 1 ? a(M_K, k) * dx : 0.0) + a(M_KF, k);
                 a(M_DUA, k) = dua;
@@ -236,7 +236,7 @@ __device__ int ms_qp(const DevParams& p, const MsArr<NMAX>& a, int N, int& iters
             }
         }
         double maff = 0.0;
-        #pragma unroll 1
+        #pragma unroll 4
         for (int k = 0; k < N; ++k) {
             const double dua = a(M_DUA, k);
             const double du = a(M_DU, k), nl = a(M_NL, k), nu = a(M_NU, k);
@@ -251,7 +251,7 @@ __device__ int ms_qp(const DevParams& p, const MsArr<NMAX>& a, int N, int& iters
         // backward corrector: the Riccati vectors with the centred,
         // second-order-corrected complementarity targets
         pn = rxN;
-        #pragma unroll 1
+        #pragma unroll 4
         for (int k = N - 1; k >= 0; --k) {
             const double A = a(M_A, k), B = a(M_B, k);
             const double du = a(M_DU, k), nl = a(M_NL, k), nu = a(M_NU, k), mu = a(M_MU, k);
@@ -282,7 +282,7 @@ __device__ int ms_qp(const DevParams& p, const MsArr<NMAX>& a, int N, int& iters
         #pragma unroll 1
         for (int pass = 0; pass < 2; ++pass) {
             double dx = 0.0;
-            #pragma unroll 1
+            #pragma unroll 4
             for (int k = 0; k < N; ++k) {
                 const double A = a(M_A, k), B = a(M_B, k);
                 const double ddu = (k >= 1 ? a(M_K, k) * dx : 0.0) + a(M_KF, k);
@@ -347,7 +347,7 @@ __device__ bool ms_sqp(const DevParams& p, const MsArr<NMAX>& a, int N, double x
     {
         // feasible start: the states follow the inputs; W^[0] = I
         double xk = x0;
-        #pragma unroll 1
+        #pragma unroll 4
         for (int k = 0; k < N; ++k) {
             double u = a(M_U, k);
             if (u < p.umin) u = p.umin;
@@ -380,7 +380,7 @@ __device__ bool ms_sqp(const DevParams& p, const MsArr<NMAX>& a, int N, double x
         // eq. (convergence): |grad L / s_d|_inf <= eps and |c|_inf <= eps
         double s1 = 0.0, gmax = 0.0, cmax = 0.0;
         bool bad = false;
-        #pragma unroll 1
+        #pragma unroll 4
         for (int k = 0; k < N; ++k) {
             const double lam = a(M_LAM, k), pl = a(M_PIL, k), pu = a(M_PIU, k);
             s1 += fabs(lam) + fabs(pl) + fabs(pu);
@@ -396,7 +396,7 @@ __device__ bool ms_sqp(const DevParams& p, const MsArr<NMAX>& a, int N, double x
         if (l == p.sqp_max_iter) return false;
         // QP; an indefinite block (or H_uu <= 0 in the recursion) resets W
         bool pd = true;
-        #pragma unroll 1
+        #pragma unroll 4
         for (int k = 0; k < N; ++k) {
             const double wuu = a(M_WUU, k), wxx = a(M_WXX, k);
             pd = pd && wuu > 0.0 && wxx > 0.0;
@@ -409,7 +409,7 @@ __device__ bool ms_sqp(const DevParams& p, const MsArr<NMAX>& a, int N, double x
         cnt[C_IPM] += it;
         if (st == -1) {
             cnt[C_RESET]++;
-            #pragma unroll 1
+            #pragma unroll 4
             for (int k = 0; k < N; ++k) {
                 a(M_WXX, k) = 1.0;
                 a(M_WXU, k) = 0.0;
@@ -422,7 +422,7 @@ __device__ bool ms_sqp(const DevParams& p, const MsArr<NMAX>& a, int N, double x
         cnt[C_SQP]++;
         // Powell's l1 merit: sigma = |mu| first, then max(|mu|, (sigma + |mu|)/2)
         double T0 = f, D = 0.0;
-        #pragma unroll 1
+        #pragma unroll 4
         for (int k = 0; k < N; ++k) {
             const double am = fabs(a(M_MU, k));
             const double sg = first ? am : fmax(am, 0.5 * (a(M_SIG, k) + am));
@@ -573,14 +573,14 @@ __global__ __launch_bounds__(64) void nmpc_ms_kernel(DevParams p, MsWork wk, Out
             cnt[C_OCP]++;
             if (!conv) cnt[C_OCP_FAIL]++;
             uint64_t mask = 0;
-            #pragma unroll 1
+            #pragma unroll 4
             for (int k = 0; k < N; ++k) {
                 const double v = a(M_U, k);
                 if (v <= p.umin + 1e-6 || v >= p.umax - 1e-6) mask |= (1ull << k);
             }
             hsh = fnv1a_step(hsh, (uint32_t)i, mask);
             const double F = a(M_U, 0) / kMlMinPerLs;
-            #pragma unroll 1
+            #pragma unroll 4
             for (int k = 0; k + 1 < N; ++k) a(M_U, k) = a(M_U, k + 1);
             if (out.tu) out.tu[(int64_t)i * out.S + pos] = F;
             #pragma unroll 1
