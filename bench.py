@@ -197,7 +197,10 @@ def main():
     phi, stats = camp.costs()
     ms_kernels = camp.kernel_ms()
     ms_per_step = (t1 - t0) * 1000.0 / args.steps
-    n_nmpc, n_pi = stats["count"]
+    # samples per controller (all of them: a diverged closed loop counts as
+    # simulated, though the Phi statistics leave it out)
+    n_pi = stats["totals"]["kind"]
+    n_nmpc = S - n_pi
     value = n_nmpc / (ms_per_step / 1000.0) if n_nmpc else S / (ms_per_step / 1000.0)
     tot = stats["totals"]
     plan = camp.plan()
@@ -373,7 +376,8 @@ def side_runs(cfg):
     dt = time.perf_counter() - t0
     _, st = camp.costs()
     tot = st["totals"]
-    res["eps_1e-8"] = dict(nmpc_sims_per_s=round(st["count"][0] / dt, 3), ms_per_step=round(dt * 1e3, 3),
+    n_nm = c8["n_samples"] - tot["kind"]
+    res["eps_1e-8"] = dict(nmpc_sims_per_s=round(n_nm / dt, 3), ms_per_step=round(dt * 1e3, 3),
                            nmpc_kernel_ms=round(camp.kernel_ms()[0], 3), ocp_total=tot["n_ocp"],
                            ocp_failed=tot["n_ocp_fail"],
                            sqp_iter_per_ocp=round(tot["sqp_iter"] / max(1, tot["n_ocp"]), 3))

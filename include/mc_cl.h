@@ -59,7 +59,10 @@ enum {
     MC_CL_CNT_BFGS_SKIP,     /* BFGS updates skipped (kappa <= eps_m)           */
     MC_CL_CNT_BFGS_RESET,    /* W reset to I after a non-positive pivot         */
     MC_CL_CNT_IPM_CAP,       /* QPs that hit the interior-point iteration cap   */
-    MC_CL_CNT_NONFINITE,     /* 1 if a non-finite state appeared                */
+    MC_CL_CNT_NONFINITE,     /* 1 if a non-finite state appeared; an NMPC
+                                sample whose plant output stops being finite
+                                ends its closed loop there (Phi is NaN, no
+                                further OCP is solved)                       */
     MC_CL_CNT_GRAD,          /* objective-gradient evaluations                  */
     MC_CL_CNT_AS_ITER,       /* active-set QP iterations (linear solves)        */
     MC_CL_NCNT
@@ -214,7 +217,9 @@ typedef struct {
                                  entry with the three-state model)             */
 } mc_cl_outputs;
 
-/* Campaign statistics (per controller: index 0 NMPC, 1 PI).                 */
+/* Campaign statistics (per controller: index 0 NMPC, 1 PI), over the
+ * samples whose Phi is finite (a diverged closed loop, see
+ * MC_CL_CNT_NONFINITE, is left out and counted in totals).                  */
 typedef struct {
     int64_t count[2];
     double mean[2];           /* mean Phi                                      */

@@ -1053,6 +1053,12 @@ void oc_run_sample_ext(const oc_params *p, int64_t sample_id, const int32_t *ov,
         if (tangent)
             for (b = 0; b < 2; ++b) dphi[b] += 2.0 * (z - zb_i) * dn[2][b] / p->V;
         if (i == su.L) break;
+        if (su.kind == 0 && !isfinite(z)) {
+            /* the plant diverged: Phi is not a number and no further OCP
+             * is solved                                                     */
+            out->nonfinite = 1;
+            break;
+        }
         /* measurement y_i = c_T(t_i) + v_i, v ~ N(0, R)                     */
         oc_normal_pair(p->seed, 0, (uint32_t)i, id32(su.noise_id), TAG_MEAS, xi);
         y = z + p->noise_scale * sqrtR * xi[0];
@@ -1224,7 +1230,8 @@ void oc_run_ov(const oc_params *p, const int64_t *ids, const int32_t *ov, int64_
 }
 
 /* ------------------------------------------------------------------------
- * Distribution of Phi, eq. (Phi) over samples: mean, sample variance
+ * Distribution of Phi, eq. (Phi) over the samples whose Phi is finite (a
+ * diverged closed loop has none): mean, sample variance
  * (divisor n-1), both with Neumaier-compensated sums; histogram of log10 Phi
  * in 200 equal bins on [-4, 4), left-closed, hist[0] = underflow, hist[201]
  * = overflow.                                                               */
@@ -1239,15 +1246,19 @@ static void neumaier_add(double *sum, double *comp, double v)
 void oc_stats(const double *phi, int64_t n, double *mean, double *var, int64_t *hist)
 {
     double s = 0.0, c = 0.0, m, s2 = 0.0, c2 = 0.0;
-    int64_t i;
+    int64_t i, nf = 0;
     for (i = 0; i < 202; ++i) hist[i] = 0;
-    for (i = 0; i < n; ++i) neumaier_add(&s, &c, phi[i]);
-    m = (s + c) / (double)n;
-    for (i = 0; i < n; ++i) neumaier_add(&s2, &c2, (phi[i] - m) * (phi[i] - m));
+    for (i = 0; i < n; ++i)
+        if (isfinite(phi[i])) { neumaier_add(&s, &c, phi[i]); nf++; }
+    m = nf > 0 ? (s + c) / (double)nf : 0.0;
+    for (i = 0; i < n; ++i)
+        if (isfinite(phi[i])) neumaier_add(&s2, &c2, (phi[i] - m) * (phi[i] - m));
     *mean = m;
-    *var = n > 1 ? (s2 + c2) / (double)(n - 1) : 0.0;
+    *var = nf > 1 ? (s2 + c2) / (double)(nf - 1) : 0.0;
     for (i = 0; i < n; ++i) {
-        double v = log10(phi[i]);
+        double v;
+        if (!isfinite(phi[i])) continue;
+        v = log10(phi[i]);
         if (!(v >= -4.0)) hist[0]++;
         else if (v >= 4.0) hist[201]++;
         else {

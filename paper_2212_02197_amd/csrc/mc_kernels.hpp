@@ -737,15 +737,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
             #pragma unroll 1
             for (int k = 0; k < N; ++k) U[te(k)] = su.ubar * kMlMinPerLs;
         const int Lmax = wave_max_i(L);
+        int Lrun = L;   // cut short when the plant state stops being finite
         for (int i = 0; i <= Lmax; ++i) {
-            const bool live = has && i <= L;
-            const bool step = live && i < L;
+            const bool live = has && i <= Lrun;
+            bool step = live && i < Lrun;
             double z = 0.0;
             if (live) {
                 z = n[2] / p.V;
                 const double zb = setpoint(p, i, su.istep, su.sign);
                 phiacc += (z - zb) * (z - zb);
                 if (out.tz) out.tz[(int64_t)i * out.S + pos] = z;
+                if (!isfinite(z)) {
+                    // the plant diverged (Phi is not a number): no more OCPs
+                    cnt[C_NONFIN] = 1;
+                    Lrun = i;
+                    step = false;
+                }
             }
             if (step) {
                 const double y = z + p.noise_scale * sqrtR *
@@ -1063,7 +1070,7 @@ __global__ __launch_bounds__(1024) void stats_kernel(const double* phi, const in
         double a = 0.0;
         long long k = 0;
         for (int64_t s = t; s < S; s += 1024)
-            if (kind[s] == c) { a += phi[s]; ++k; }
+            if (kind[s] == c && isfinite(phi[s])) { a += phi[s]; ++k; }
         sh[t] = a;
         sh2[t] = (double)k;
         __syncthreads();
@@ -1078,7 +1085,7 @@ __global__ __launch_bounds__(1024) void stats_kernel(const double* phi, const in
     for (int c = 0; c < 2; ++c) {
         double a = 0.0;
         for (int64_t s = t; s < S; s += 1024)
-            if (kind[s] == c) {
+            if (kind[s] == c && isfinite(phi[s])) {
                 const double dlt = phi[s] - mean[c];
                 a += dlt * dlt;
                 const double v = log10(phi[s]);

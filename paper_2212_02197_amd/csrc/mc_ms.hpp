@@ -145,25 +145,46 @@ __device__ __forceinline__ int ms_bfgs2(double& a, double& b, double& c, double 
 // mean complementarity <= 1e-14 (1 + |fx|) (infinity norms), or ipm_max_iter
 // iterations.  Returns 0 converged, 1 iteration cap, -1 an H_uu <= 0 (W not
 // positive definite).  Results in DU, DX, MU, NL, NU.
-template <int NMAX>
-__device__ int ms_qp(const DevParams& p, const MsArr<NMAX>& a, int N, int& iters) {
+// The stage arrays arrive as separate restrict-qualified pointers (element
+// k at [k * 64]): no store of one sweep can alias another array's load,
+// so the unrolled sweeps issue the loads of several stages together.
+__device__ __forceinline__ int ms_qp_body(const DevParams& p, int N, int& iters,
+                                         const double* __restrict__ gU,
+                                         const double* __restrict__ gA,
+                                         const double* __restrict__ gB,
+                                         const double* __restrict__ gC,
+                                         const double* __restrict__ gFX,
+                                         const double* __restrict__ gWXX,
+                                         const double* __restrict__ gWXU,
+                                         const double* __restrict__ gWUU,
+                                         double* __restrict__ gDU,
+                                         double* __restrict__ gDX,
+                                         double* __restrict__ gMU,
+                                         double* __restrict__ gNL,
+                                         double* __restrict__ gNU,
+                                         double* __restrict__ gK,
+                                         double* __restrict__ gHI,
+                                         double* __restrict__ gP,
+                                         double* __restrict__ gKF,
+                                         double* __restrict__ gPV,
+                                         double* __restrict__ gDUA) {
     double gsc = 0.0;
     {
         double dx = 0.0;
         #pragma unroll 4
         for (int k = 0; k < N; ++k) {
-            const double lo = p.umin - a(M_U, k), hi = p.umax - a(M_U, k);
+            const double lo = p.umin - gU[(k) * 64], hi = p.umax - gU[(k) * 64];
             const double dl = 1e-2 * (hi - lo);
             double du = 0.0;
             if (du < lo + dl) du = lo + dl;
             if (du > hi - dl) du = hi - dl;
-            a(M_DU, k) = du;
-            a(M_NL, k) = 1.0;
-            a(M_NU, k) = 1.0;
-            a(M_MU, k) = 0.0;
-            dx = a(M_A, k) * dx + a(M_B, k) * du + a(M_C, k);
-            a(M_DX, k) = dx;
-            gsc = fmax(gsc, fabs(a(M_FX, k)));
+            gDU[(k) * 64] = du;
+            gNL[(k) * 64] = 1.0;
+            gNU[(k) * 64] = 1.0;
+            gMU[(k) * 64] = 0.0;
+            dx = gA[(k) * 64] * dx + gB[(k) * 64] * du + gC[(k) * 64];
+            gDX[(k) * 64] = dx;
+            gsc = fmax(gsc, fabs(gFX[(k) * 64]));
         }
     }
     const double inv2N = 1.0 / (2.0 * N);
@@ -172,17 +193,17 @@ __device__ int ms_qp(const DevParams& p, const MsArr<NMAX>& a, int N, int& iters
         // backward sweep: residuals of the current point, their norms, the
         // Riccati factors and the predictor's vectors (complementarity
         // target 0)
-        double Pn = a(M_WXX, N - 1);
-        double rxN = a(M_WXX, N - 1) * a(M_DX, N - 1) + a(M_FX, N - 1) + a(M_MU, N - 1);
+        double Pn = gWXX[(N - 1) * 64];
+        double rxN = gWXX[(N - 1) * 64] * gDX[(N - 1) * 64] + gFX[(N - 1) * 64] + gMU[(N - 1) * 64];
         double pn = rxN;
-        double rmax = fabs(rxN), wd = fabs(a(M_WXX, N - 1) * a(M_DX, N - 1)), comp = 0.0;
+        double rmax = fabs(rxN), wd = fabs(gWXX[(N - 1) * 64] * gDX[(N - 1) * 64]), comp = 0.0;
         #pragma unroll 4
         for (int k = N - 1; k >= 0; --k) {
-            const double A = a(M_A, k), B = a(M_B, k);
-            const double du = a(M_DU, k), nl = a(M_NL, k), nu = a(M_NU, k), mu = a(M_MU, k);
-            const double dxk = k >= 1 ? a(M_DX, k - 1) : 0.0;
-            const double wuu = a(M_WUU, k), wxu = k >= 1 ? a(M_WXU, k) : 0.0;
-            const double lo = p.umin - a(M_U, k), hi = p.umax - a(M_U, k);
+            const double A = gA[(k) * 64], B = gB[(k) * 64];
+            const double du = gDU[(k) * 64], nl = gNL[(k) * 64], nu = gNU[(k) * 64], mu = gMU[(k) * 64];
+            const double dxk = k >= 1 ? gDX[(k - 1) * 64] : 0.0;
+            const double wuu = gWUU[(k) * 64], wxu = k >= 1 ? gWXU[(k) * 64] : 0.0;
+            const double lo = p.umin - gU[(k) * 64], hi = p.umax - gU[(k) * 64];
             const double tl = du - lo, tu = hi - du;
             const double wdu = wuu * du + wxu * dxk;
             const double ru = wdu - mu * B - nl + nu;
@@ -194,19 +215,19 @@ __device__ int ms_qp(const DevParams& p, const MsArr<NMAX>& a, int N, int& iters
             if (!(Huu > 0.0)) { iters = it; return -1; }
             const double hinv = 1.0 / Huu;
             const double kf = -(rt + B * e) * hinv;
-            a(M_HI, k) = hinv;
-            a(M_KF, k) = kf;
-            a(M_P, k) = Pn;
-            a(M_PV, k) = pn;
+            gHI[(k) * 64] = hinv;
+            gKF[(k) * 64] = kf;
+            gP[(k) * 64] = Pn;
+            gPV[(k) * 64] = pn;
             rmax = fmax(rmax, fabs(ru));
             wd = fmax(wd, fabs(wdu));
             if (k >= 1) {
-                const double wxx = a(M_WXX, k - 1);
+                const double wxx = gWXX[(k - 1) * 64];
                 const double wdx = wxx * dxk + wxu * du;
-                const double rx = wdx + a(M_FX, k - 1) - mu * A + a(M_MU, k - 1);
+                const double rx = wdx + gFX[(k - 1) * 64] - mu * A + gMU[(k - 1) * 64];
                 const double Hux = wxu + B * Pn * A;
                 const double K = -Hux * hinv;
-                a(M_K, k) = K;
+                gK[(k) * 64] = K;
                 Pn = wxx + A * A * Pn + Hux * K;
                 pn = rx + A * e + Hux * kf;
                 rmax = fmax(rmax, fabs(rx));
@@ -222,25 +243,25 @@ __device__ int ms_qp(const DevParams& p, const MsArr<NMAX>& a, int N, int& iters
             double dx = 0.0;
             #pragma unroll 4
             for (int k = 0; k < N; ++k) {
-                const double dua = (k >= 1 ? a(M_K, k) * dx : 0.0) + a(M_KF, k);
-                a(M_DUA, k) = dua;
-                const double du = a(M_DU, k), nl = a(M_NL, k), nu = a(M_NU, k);
-                const double lo = p.umin - a(M_U, k), hi = p.umax - a(M_U, k);
+                const double dua = (k >= 1 ? gK[(k) * 64] * dx : 0.0) + gKF[(k) * 64];
+                gDUA[(k) * 64] = dua;
+                const double du = gDU[(k) * 64], nl = gNL[(k) * 64], nu = gNU[(k) * 64];
+                const double lo = p.umin - gU[(k) * 64], hi = p.umax - gU[(k) * 64];
                 const double tl = du - lo, tu = hi - du;
                 const double dnl = -nl - nl * dua / tl, dnu = -nu + nu * dua / tu;
                 if (dua < 0.0) apr = fmin(apr, -tl / dua);
                 if (dua > 0.0) apr = fmin(apr, tu / dua);
                 if (dnl < 0.0) adr = fmin(adr, -nl / dnl);
                 if (dnu < 0.0) adr = fmin(adr, -nu / dnu);
-                dx = a(M_A, k) * dx + a(M_B, k) * dua;
+                dx = gA[(k) * 64] * dx + gB[(k) * 64] * dua;
             }
         }
         double maff = 0.0;
         #pragma unroll 4
         for (int k = 0; k < N; ++k) {
-            const double dua = a(M_DUA, k);
-            const double du = a(M_DU, k), nl = a(M_NL, k), nu = a(M_NU, k);
-            const double lo = p.umin - a(M_U, k), hi = p.umax - a(M_U, k);
+            const double dua = gDUA[(k) * 64];
+            const double du = gDU[(k) * 64], nl = gNL[(k) * 64], nu = gNU[(k) * 64];
+            const double lo = p.umin - gU[(k) * 64], hi = p.umax - gU[(k) * 64];
             const double tl = du - lo, tu = hi - du;
             const double dnl = -nl - nl * dua / tl, dnu = -nu + nu * dua / tu;
             maff += (tl + apr * dua) * (nl + adr * dnl) + (tu - apr * dua) * (nu + adr * dnu);
@@ -253,25 +274,25 @@ __device__ int ms_qp(const DevParams& p, const MsArr<NMAX>& a, int N, int& iters
         pn = rxN;
         #pragma unroll 4
         for (int k = N - 1; k >= 0; --k) {
-            const double A = a(M_A, k), B = a(M_B, k);
-            const double du = a(M_DU, k), nl = a(M_NL, k), nu = a(M_NU, k), mu = a(M_MU, k);
-            const double dxk = k >= 1 ? a(M_DX, k - 1) : 0.0;
-            const double wuu = a(M_WUU, k), wxu = k >= 1 ? a(M_WXU, k) : 0.0;
-            const double lo = p.umin - a(M_U, k), hi = p.umax - a(M_U, k);
+            const double A = gA[(k) * 64], B = gB[(k) * 64];
+            const double du = gDU[(k) * 64], nl = gNL[(k) * 64], nu = gNU[(k) * 64], mu = gMU[(k) * 64];
+            const double dxk = k >= 1 ? gDX[(k - 1) * 64] : 0.0;
+            const double wuu = gWUU[(k) * 64], wxu = k >= 1 ? gWXU[(k) * 64] : 0.0;
+            const double lo = p.umin - gU[(k) * 64], hi = p.umax - gU[(k) * 64];
             const double tl = du - lo, tu = hi - du;
             const double ru = wuu * du + wxu * dxk - mu * B - nl + nu;
-            const double dua = a(M_DUA, k);
+            const double dua = gDUA[(k) * 64];
             const double dnla = -nl - nl * dua / tl, dnua = -nu + nu * dua / tu;
             const double taul = smu - dua * dnla, tauu = smu + dua * dnua;
             const double rt = ru + nl - taul / tl - nu + tauu / tu;
-            const double Pn1 = a(M_P, k);
+            const double Pn1 = gP[(k) * 64];
             const double e = pn;
-            const double kf = -(rt + B * e) * a(M_HI, k);
-            a(M_KF, k) = kf;
-            a(M_PV, k) = pn;
+            const double kf = -(rt + B * e) * gHI[(k) * 64];
+            gKF[(k) * 64] = kf;
+            gPV[(k) * 64] = pn;
             if (k >= 1) {
-                const double wxx = a(M_WXX, k - 1);
-                const double rx = wxx * dxk + wxu * du + a(M_FX, k - 1) - mu * A + a(M_MU, k - 1);
+                const double wxx = gWXX[(k - 1) * 64];
+                const double rx = wxx * dxk + wxu * du + gFX[(k - 1) * 64] - mu * A + gMU[(k - 1) * 64];
                 const double Hux = wxu + B * Pn1 * A;
                 pn = rx + A * e + Hux * kf;
             }
@@ -284,14 +305,14 @@ __device__ int ms_qp(const DevParams& p, const MsArr<NMAX>& a, int N, int& iters
             double dx = 0.0;
             #pragma unroll 4
             for (int k = 0; k < N; ++k) {
-                const double A = a(M_A, k), B = a(M_B, k);
-                const double ddu = (k >= 1 ? a(M_K, k) * dx : 0.0) + a(M_KF, k);
+                const double A = gA[(k) * 64], B = gB[(k) * 64];
+                const double ddu = (k >= 1 ? gK[(k) * 64] * dx : 0.0) + gKF[(k) * 64];
                 const double ddx = A * dx + B * ddu;
-                const double dmu = -(a(M_P, k) * ddx + a(M_PV, k));
-                const double du = a(M_DU, k), nl = a(M_NL, k), nu = a(M_NU, k);
-                const double lo = p.umin - a(M_U, k), hi = p.umax - a(M_U, k);
+                const double dmu = -(gP[(k) * 64] * ddx + gPV[(k) * 64]);
+                const double du = gDU[(k) * 64], nl = gNL[(k) * 64], nu = gNU[(k) * 64];
+                const double lo = p.umin - gU[(k) * 64], hi = p.umax - gU[(k) * 64];
                 const double tl = du - lo, tu = hi - du;
-                const double dua = a(M_DUA, k);
+                const double dua = gDUA[(k) * 64];
                 const double dnla = -nl - nl * dua / tl, dnua = -nu + nu * dua / tu;
                 const double taul = smu - dua * dnla, tauu = smu + dua * dnua;
                 const double dnl = (-tl * nl + taul - nl * ddu) / tl;
@@ -302,11 +323,11 @@ __device__ int ms_qp(const DevParams& p, const MsArr<NMAX>& a, int N, int& iters
                     if (dnl < 0.0) ad = fmin(ad, -nl / dnl);
                     if (dnu < 0.0) ad = fmin(ad, -nu / dnu);
                 } else {
-                    a(M_DU, k) = du + ap * ddu;
-                    a(M_DX, k) = a(M_DX, k) + ap * ddx;
-                    a(M_MU, k) = a(M_MU, k) + ad * dmu;
-                    a(M_NL, k) = nl + ad * dnl;
-                    a(M_NU, k) = nu + ad * dnu;
+                    gDU[(k) * 64] = du + ap * ddu;
+                    gDX[(k) * 64] = gDX[(k) * 64] + ap * ddx;
+                    gMU[(k) * 64] = gMU[(k) * 64] + ad * dmu;
+                    gNL[(k) * 64] = nl + ad * dnl;
+                    gNU[(k) * 64] = nu + ad * dnu;
                 }
                 dx = ddx;
             }
@@ -316,6 +337,12 @@ __device__ int ms_qp(const DevParams& p, const MsArr<NMAX>& a, int N, int& iters
             }
         }
     }
+}
+
+template <int NMAX>
+__device__ int ms_qp(const DevParams& p, const MsArr<NMAX>& a, int N, int& iters) {
+    auto g = [&](int m) { return &a(m, 0); };
+    return ms_qp_body(p, N, iters, g(M_U), g(M_A), g(M_B), g(M_C), g(M_FX), g(M_WXX), g(M_WXU), g(M_WUU), g(M_DU), g(M_DX), g(M_MU), g(M_NL), g(M_NU), g(M_K), g(M_HI), g(M_P), g(M_KF), g(M_PV), g(M_DUA));
 }
 
 // Merit of the trial point xi + alpha dxi: f + sigma^T |c| (value-only
@@ -554,14 +581,21 @@ __global__ __launch_bounds__(64) void nmpc_ms_kernel(DevParams p, MsWork wk, Out
             #pragma unroll 1
             for (int k = 0; k < N; ++k) a(M_U, k) = su.ubar * kMlMinPerLs;
         const int Lmax = wave_max_i(L);
+        int Lrun = L;   // cut short when the plant state stops being finite
         for (int i = 0; i <= Lmax; ++i) {
-            const bool live = has && i <= L;
-            const bool step = live && i < L;
+            const bool live = has && i <= Lrun;
+            const bool step = live && i < Lrun;
             if (!live) continue;
             const double z = n[2] / p.V;
             const double zb = setpoint(p, i, su.istep, su.sign);
             phiacc += (z - zb) * (z - zb);
             if (out.tz) out.tz[(int64_t)i * out.S + pos] = z;
+            if (!isfinite(z)) {
+                // the plant diverged (Phi is not a number): no more OCPs
+                cnt[C_NONFIN] = 1;
+                Lrun = i;
+                continue;
+            }
             if (!step) continue;
             const double y = z + p.noise_scale * sqrtR *
                                      normal_first(p.seed, 0, (uint32_t)i, su.nid, kTagMeas);

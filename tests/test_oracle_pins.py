@@ -602,3 +602,18 @@ def test_scenario_draws_lognormal_kinetics(oracle):
     # without the perturbation the plant keeps the nominal kinetics
     nom = oracle.scenario(W.c0_small_nmpc(), 7)
     assert nom["k0"] == cfg["k0"] and nom["EaR"] == cfg["EaR"]
+
+
+def test_diverged_plant_ends_the_nmpc_closed_loop(oracle):
+    # c3 id 1937: E_a/R drawn 3.9 sigma low makes the plant stiff beyond the
+    # Euler-Maruyama sub-step, which diverges in the first interval.  The
+    # closed loop stops there: Phi NaN, the flag set, only the OCPs before
+    # the divergence solved; the statistics skip the sample.
+    cfg = W.c3_uneven()
+    r = oracle.run_sample(cfg, 1937)
+    assert oracle.scenario(cfg, 1937)["EaR"] < 0.83 * cfg["EaR"]
+    assert math.isnan(r["phi"]) and r["nonfinite"] == 1
+    assert r["n_ocp"] <= 2 < r["L"]
+    ok = oracle.run_sample(cfg, 1938)["phi"]
+    m, v, h = oracle.stats(np.array([r["phi"], ok, ok]))
+    assert m == ok and v == 0.0 and h.sum() == 2
