@@ -423,10 +423,12 @@ def adjoint_vs_plain(cfg, n):
                          sqp_iter_per_ocp=round(st["totals"]["sqp_iter"] / st["totals"]["n_ocp"], 3))
         camp.close()
         log(f"{name} gradient: {n} NMPC samples in {dt:.2f} s")
-    rel = np.abs(phis["adjoint"][0] - phis["plain"][0]) / np.abs(phis["plain"][0])
+    fin = np.isfinite(phis["adjoint"][0]) & np.isfinite(phis["plain"][0])
+    rel = np.abs(phis["adjoint"][0][fin] - phis["plain"][0][fin]) / np.abs(phis["plain"][0][fin])
     res["samples"] = n
+    res["diverged_samples"] = int((~fin).sum())
     res["speedup_adjoint_over_plain"] = round(res["adjoint"]["sims_per_s"] / res["plain"]["sims_per_s"], 4)
-    res["max_rel_phi_diff"] = float(rel.max())
+    res["max_rel_phi_diff"] = float(rel.max()) if rel.size else 0.0
     res["active_set_flips"] = int((phis["adjoint"][1] != phis["plain"][1]).sum())
     return res
 

@@ -56,6 +56,7 @@ class Params(C.Structure):
         ("sample_ids", C.c_void_p), ("kind", C.c_void_p), ("horizon", C.c_void_p),
         ("lengths", C.c_void_p), ("nlp_form", C.c_int32),
         ("workspace", C.c_void_p), ("workspace_size", C.c_size_t),
+        ("class_streams", C.c_int32),
     ]
 
 
@@ -181,6 +182,7 @@ def params(cfg: dict, arrays: dict = None) -> Params:
     p.cu_limit = cfg.get("cu_limit", 0)
     p.model_nx = cfg.get("model_nx", 1)
     p.nlp_form = cfg.get("nlp_form", 0)
+    p.class_streams = cfg.get("class_streams", 0)
     for a in range(3):
         p.sigma[a] = cfg["sigma"][a]
     sp_i, sp_z = cfg["sp_i"], cfg["sp_z"]

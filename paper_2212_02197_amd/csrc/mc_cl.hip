@@ -405,6 +405,7 @@ static int validate(const mc_cl_params* p) {
     if (p->nlp_form == 1 && p->model_nx != 1) return MC_CL_EUNSUPPORTED;
     if (p->workspace && (p->workspace_size == 0 || ((uintptr_t)p->workspace & 255u) != 0))
         return MC_CL_EINVAL;
+    if (p->class_streams != 0 && p->class_streams != 1) return MC_CL_EINVAL;
     if (!p->sample_ids &&
         (p->sample_id_offset < 0 || p->sample_id_offset + p->n_samples > (int64_t)UINT32_MAX))
         return MC_CL_EINVAL;
@@ -457,7 +458,7 @@ static int size_ckpt(mc_cl_ctx* c, int C) {
     const int64_t nseg = std::max<int64_t>((c->Lmax + C - 1) / C, 1);
     int rc;
     if ((rc = c->realloc_dev(&c->d_ck, (size_t)nseg * 4 * c->n_pi)) ||
-        (rc = c->realloc_dev(&c->d_tape, (size_t)C * c->prm.Ns * 3 * c->n_pi)) ||
+        (rc = c->realloc_dev(&c->d_tape, (size_t)C * c->prm.Ns * 6 * c->n_pi)) ||
         (rc = c->realloc_dev(&c->d_ivtape, (size_t)C * 5 * c->n_pi)))
         return rc;
     c->ckC = C;
@@ -490,11 +491,13 @@ static int launch_step(mc_cl_ctx* c, hipStream_t st, const Outs& out, bool chunk
         hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, c->d_queue, 4, 0);
         HIPCHK(hipGetLastError());
     }
-    // Horizon classes run concurrently (unchunked runs on the whole device):
-    // the waves of one class's launch take the SIMDs that another's tail
-    // leaves idle, as one persistent launch over all classes would.  Their
-    // queues, workspaces and output positions are disjoint.
-    const bool conc = !chunk && c->classes.size() > 1 && c->prm.cu_limit == 0 && c->fork;
+    // With class_streams the horizon classes run concurrently (unchunked
+    // runs on the whole device): the waves of one class's launch take the
+    // SIMDs that another's tail leaves idle, as one persistent launch over
+    // all classes would.  Their queues, workspaces and output positions are
+    // disjoint.  Otherwise one after another on `st`.
+    const bool conc = !chunk && c->classes.size() > 1 && c->prm.cu_limit == 0 &&
+                      c->prm.class_streams == 1 && c->fork;
     if (conc) {
         HIPCHK(hipEventRecord(c->fork, st));
         for (size_t k = 1; k < c->classes.size(); ++k)
@@ -816,7 +819,7 @@ int mc_cl_run(mc_cl_ctx* c, void* hip_stream, const mc_cl_outputs* o) {
         for (int k = 0; k < c->n_chunks; ++k) HIPCHK(hipGraphLaunch(c->gexec, st));
         HIPCHK(hipEventRecord(c->ev[1], st));
     } else {
-        if (c->classes.size() > 1 && c->prm.cu_limit == 0) {
+        if (c->classes.size() > 1 && c->prm.cu_limit == 0 && c->prm.class_streams == 1) {
             const int rc = c->ensure_side();
             if (rc != MC_CL_OK) return rc;
         }

@@ -921,9 +921,12 @@ __global__ __launch_bounds__(64) void pi_kernel(DevParams p, const int64_t* pos_
 
 // Reverse pass of the PI closed loop (pathwise, noise held fixed) from the
 // checkpoints: each segment of C intervals is recomputed forward with its
-// per-sub-step plant states taped (tape[(step * 3 + f) * npi + t]), then
-// swept backwards, drawing each sub-step's noise again from its counter.
-// Writes dPhi/dkP and dPhi/dkI per sample.
+// per-sub-step states and noise taped (tape[(step * 6 + f) * npi + t]),
+// then swept backwards.  (Drawing the noise again in the reverse sweep
+// instead of taping it halves the tape but adds two Philox blocks and a
+// Box-Muller pair to each lane's serial chain: c2's reverse pass took
+// 48.9 ms that way against 35.1 ms taped.)  Writes dPhi/dkP and dPhi/dkI
+// per sample.
 __global__ __launch_bounds__(64) void pi_reverse_kernel(DevParams p, const int64_t* pos_list,
                                                         int64_t npi, const double* ck,
                                                         double* tape, double* iv_tape,
@@ -976,9 +979,12 @@ __global__ __launch_bounds__(64) void pi_reverse_kernel(DevParams p, const int64
                 double xi[3];
                 process_noise(p, (uint32_t)(i * p.Ns + j), su.nid, xi);
                 const int64_t st = (int64_t)li * p.Ns + j;
-                tape[(st * 3 + 0) * npi + t] = n[0];
-                tape[(st * 3 + 1) * npi + t] = n[1];
-                tape[(st * 3 + 2) * npi + t] = n[2];
+                tape[(st * 6 + 0) * npi + t] = n[0];
+                tape[(st * 6 + 1) * npi + t] = n[1];
+                tape[(st * 6 + 2) * npi + t] = n[2];
+                tape[(st * 6 + 3) * npi + t] = xi[0];
+                tape[(st * 6 + 4) * npi + t] = xi[1];
+                tape[(st * 6 + 5) * npi + t] = xi[2];
                 em_step(p, su.k0, su.EaR, n, uk, h, sqh, xi);
             }
         }
@@ -1011,14 +1017,12 @@ __global__ __launch_bounds__(64) void pi_reverse_kernel(DevParams p, const int64
             #pragma unroll 1
             for (int j = p.Ns - 1; j >= 0; --j) {
                 const int64_t st = (int64_t)li * p.Ns + j;
-                const double a0 = tape[(st * 3 + 0) * npi + t];
-                const double a1 = tape[(st * 3 + 1) * npi + t];
-                const double a2 = tape[(st * 3 + 2) * npi + t];
-                // the sub-step's noise is drawn again (counter-based, the
-                // same normals) rather than taped: half the tape traffic
-                double xr[3];
-                process_noise(p, (uint32_t)(i * p.Ns + j), su.nid, xr);
-                const double x0 = xr[0], x1 = xr[1], x2 = xr[2];
+                const double a0 = tape[(st * 6 + 0) * npi + t];
+                const double a1 = tape[(st * 6 + 1) * npi + t];
+                const double a2 = tape[(st * 6 + 2) * npi + t];
+                const double x0 = tape[(st * 6 + 3) * npi + t];
+                const double x1 = tape[(st * 6 + 4) * npi + t];
+                const double x2 = tape[(st * 6 + 5) * npi + t];
                 const double cA = a0 * iV, cB = a1 * iV, cT = a2 * iV;
                 const double k = su.k0 * exp(-su.EaR / cT);
                 // dr/dn = (k cB, k cA, k EaR/cT^2 cA cB) / V ; (S r V) rows S

@@ -54,6 +54,7 @@ BASE = dict(
     cu_limit=0,                    # > 0: plan for this many compute units (CU-masked stream)
     model_nx=1,                    # NMPC/EKF model: 1 the paper's one-state, 3 the three-state
     nlp_form=0,                    # OCP: 0 single shooting, 1 multiple shooting (the paper's NLP)
+    class_streams=0,               # 1: NMPC horizon classes on concurrent streams
     # optional per-sample arrays of n_samples entries (None: the rules above)
     sample_ids=None,               # global sample ids (strided subsets, any order)
     kind=None,                     # 0 NMPC, 1 PI

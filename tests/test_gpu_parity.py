@@ -472,14 +472,13 @@ def test_chunked_graph_run_matches_single_launch():
 
 
 def test_concurrent_horizon_classes_match_sequential_launches():
-    # three horizon classes (N 10 / 25 / 50) with ragged lengths: an
-    # unchunked run on the whole device launches them on concurrent streams;
-    # a positive cu_limit (here all compute units) launches them one after
-    # another on the caller's stream.  Bitwise the same results.
-    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    # three horizon classes (N 10 / 25 / 50) with ragged lengths: with
+    # class_streams an unchunked run on the whole device launches them on
+    # concurrent streams; by default one after another on the caller's
+    # stream.  Bitwise the same results.
     cfg = W.c3_uneven(n_samples=90, sample_id_offset=7000, L_lo=15, L_hi=40, samples_per_wave=8)
-    phi_c, _, ps_c, _ = gpu_run(cfg)
-    phi_s, _, ps_s, _ = gpu_run(dict(cfg, cu_limit=n_cu))
+    phi_c, _, ps_c, _ = gpu_run(dict(cfg, class_streams=1))
+    phi_s, _, ps_s, _ = gpu_run(cfg)
     assert set(ps_c["N"].tolist()) == {10, 25, 50}
     np.testing.assert_array_equal(phi_c, phi_s)
     np.testing.assert_array_equal(ps_c["ashash"], ps_s["ashash"])

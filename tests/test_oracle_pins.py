@@ -617,3 +617,19 @@ def test_diverged_plant_ends_the_nmpc_closed_loop(oracle):
     ok = oracle.run_sample(cfg, 1938)["phi"]
     m, v, h = oracle.stats(np.array([r["phi"], ok, ok]))
     assert m == ok and v == 0.0 and h.sum() == 2
+
+
+def test_stage_cost_weight_does_not_move_the_ocp_minimiser(oracle):
+    # Regulator section: the stage cost is Qz (z - zbar)^2 Ts only, so a
+    # positive Qz scales the objective and leaves its minimiser in place
+    # (a tuning of the stage cost needs a second term)
+    x0 = 318.0 * W.c1_paper_scale()["V"]
+    zbar = np.full(10, 322.0)
+    u0 = np.full(10, 400.0)
+    out = []
+    for qz in (1.0, 5.0):
+        cfg = W.c1_paper_scale(Qz=qz, sqp_eps=1e-10, sqp_max_iter=3000)
+        conv, u, _, _, _ = oracle.sqp(cfg, x0, zbar, u0)
+        assert conv
+        out.append(u)
+    np.testing.assert_allclose(out[1], out[0], rtol=1e-6, atol=1e-6)
