@@ -394,6 +394,17 @@ def side_runs(cfg):
         multiple_shooting_W0_identity=ms,
         paper_table_I="424 of 18,000,000 OCPs (0.0024 %) reach the 100-iteration cap")
     log(f"hessian start: {res['hessian_start']}")
+    # Monte Carlo tuning of the NMPC's input back-off on the same subset
+    from paper_2212_02197_amd import tuning
+    ids = np.arange(0, 30000, stride, dtype=np.int64)[:n]
+    sub = dict(cfg, n_samples=len(ids), sample_ids=ids, kind_split=-1, default_kind=0)
+    t0 = time.perf_counter()
+    sw = tuning.sweep(sub, "backoff", (0.0, 50.0, 100.0, 200.0))
+    g = tuning.crn_gradient(sub, "backoff", 100.0, 10.0)
+    res["tuning_backoff"] = dict(samples=len(ids), candidates=sw,
+                                 gradient_at_100=dict((k, g[k]) for k in ("gradient", "stderr", "step")),
+                                 wall_s=round(time.perf_counter() - t0, 3))
+    log(f"tuning: {res['tuning_backoff']}")
     return res
 
 
