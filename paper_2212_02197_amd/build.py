@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmc_cl.so")
 SOURCES = [os.path.join(CSRC, "mc_cl.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("mc_dev.hpp", "mc_coop.hpp", "mc_kernels.hpp")] + [
+DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("mc_dev.hpp", "mc_coop.hpp", "mc_kernels.hpp", "mc_ms.hpp")] + [
     os.path.join(ROOT, "include", "mc_cl.h")]
 ARCH = os.environ.get("MC_CL_ARCH", "gfx950")
 

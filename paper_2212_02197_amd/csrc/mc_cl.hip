@@ -91,18 +91,16 @@ hipError_t launch_nmpc(const DevParams& dp, const NmpcWork& wk, const Outs& o, i
     return hipGetLastError();
 }
 
-template <int NMAX>
 hipError_t launch_ms(const DevParams& dp, const NmpcWork& wk, const Outs& o, int slots,
                      hipStream_t st) {
-    MsWork mw{wk.pos, wk.n_pos, wk.n_groups, wk.queue, wk.qhi, wk.tiles, wk.tile_stride};
-    hipLaunchKernelGGL((nmpc_ms_kernel<NMAX>), dim3(slots), dim3(64), 0, st, dp, mw, o);
+    MsWork mw{wk.pos, wk.n_pos, wk.n_groups, wk.queue, wk.qhi};
+    hipLaunchKernelGGL(nmpc_ms_kernel, dim3(slots), dim3(64), 0, st, dp, mw, o);
     return hipGetLastError();
 }
 
-template <int NMAX>
 int ms_blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, nmpc_ms_kernel<NMAX>, 64, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, nmpc_ms_kernel, 64, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
@@ -119,11 +117,7 @@ int max_blocks_per_cu() {
 // Kernel variants: horizon class NMAX x gradient mode x model states; the
 // three-state model runs with the adjoint gradient only (validated).
 int blocks_per_cu(int nmax, int gmode, int nx, int nlp_form = 0) {
-    if (nlp_form == 1) {
-        if (nmax == 16) return ms_blocks_per_cu<16>();
-        if (nmax == 32) return ms_blocks_per_cu<32>();
-        return ms_blocks_per_cu<64>();
-    }
+    if (nlp_form == 1) return ms_blocks_per_cu();
     if (nx == 3) {
         if (nmax == 16) return max_blocks_per_cu<16, 1, 3>();
         if (nmax == 32) return max_blocks_per_cu<32, 1, 3>();
@@ -141,11 +135,7 @@ int blocks_per_cu(int nmax, int gmode, int nx, int nlp_form = 0) {
 
 hipError_t dispatch_nmpc(int nmax, int gmode, int nx, const DevParams& dp, const NmpcWork& wk,
                          const Outs& o, int slots, hipStream_t st) {
-    if (dp.nlp_form == 1) {
-        if (nmax == 16) return launch_ms<16>(dp, wk, o, slots, st);
-        if (nmax == 32) return launch_ms<32>(dp, wk, o, slots, st);
-        return launch_ms<64>(dp, wk, o, slots, st);
-    }
+    if (dp.nlp_form == 1) return launch_ms(dp, wk, o, slots, st);
     if (nx == 3) {
         if (nmax == 16) return launch_nmpc<16, 1, 3>(dp, wk, o, slots, st);
         if (nmax == 32) return launch_nmpc<32, 1, 3>(dp, wk, o, slots, st);
@@ -423,12 +413,12 @@ static int validate(const mc_cl_params* p) {
 // class's wave-slot workspaces when the shape needs more of them.
 static int plan_class(mc_cl_ctx* c, NmpcClass& nc, int spw) {
     const bool ms = c->prm.nlp_form == 1;
-    if (ms) spw = 64;   // one sample per lane, every lane
+    if (ms) spw = 1;   // one sample per wavefront, a stage per lane
     nc.spw = spw;
     nc.groups = (int)((nc.count + spw - 1) / spw);
     nc.slots = std::min(nc.groups, nc.slots_full);
-    // multiple shooting: the stage arrays of the slot take the tile buffer
-    nc.tile_stride = (int64_t)(ms ? (int)M_COUNT : (int)V_COUNT) * nc.nmax * 64;
+    // multiple shooting keeps every stage quantity in registers
+    nc.tile_stride = ms ? 0 : (int64_t)V_COUNT * nc.nmax * 64;
     nc.xs_stride = ms ? 0 : (int64_t)(c->prm.model_nx == 3 ? rec_width<3>() : rec_width<1>()) * nc.nmax * 64;
     nc.w_stride = ms ? 0 : (int64_t)spw * nc.nmax * nc.nmax;
     const size_t nt = (size_t)nc.slots * nc.tile_stride;
@@ -961,7 +951,7 @@ int mc_cl_tune(mc_cl_ctx* c, void* hip_stream, int32_t trial_intervals, mc_cl_tu
         NmpcClass& nc = c->classes[k];
         r->nmax[k] = nc.nmax;
         if (c->prm.nlp_form == 1) {
-            // one sample per lane: nothing to choose
+            // one sample per wavefront: nothing to choose
             for (int j = 0; j < MC_CL_TUNE_NSPW; ++j) r->nmpc_ms[k][j] = -1.0f;
             r->spw[k] = nc.spw;
             continue;

@@ -11,61 +11,113 @@
 //     indefinite block (Block BFGS update);
 //   * the scaled KKT test with the constraint residual test, eq.
 //     (convergence).
-// One-state model (the paper's case study), scalar per stage: every stage
-// quantity is a scalar and the 2x2 Hessian blocks are three numbers, so the
-// whole SQP runs one sample per lane with no cooperative work.  The stage
-// arrays of a wavefront's 64 samples live in a per-wave-slot workspace,
-// array a, stage k, lane l at ((a * NMAX + k) * 64 + l): each stage access of
-// the wave is one coalesced 512-byte row.
+// One-state model (the paper's case study).
+//
+// Layout: one sample per wavefront, stage k on lane k (N <= 64).  Every
+// stage quantity of the NLP and of the QP is one register per lane, so the
+// SQP runs without any workspace in memory:
+//   * the interval maps (values and tangents), the stage costs, the
+//     gradient of the Lagrangian, the block BFGS updates and the
+//     interior point's element-wise steps run on all stages at once, with
+//     a stage's neighbours fetched by lane shifts;
+//   * the stage recursions of the Riccati solve are parallel prefix scans
+//     over the lanes (log2 N steps): the scalar Riccati recursion of the
+//     factor P_k is a linear-fractional map of P_{k+1}, composed as 2x2
+//     matrices, and the recursions of the Riccati vector and of the
+//     forward state steps are affine maps;
+//   * sums and maxima over the stages are wavefront reductions.
+// Only the feasible start of each OCP, where the states follow the inputs
+// through the model, runs the stages one after another.
 //
 // Decision vector xi = [u_0, x_1, u_1, ..., u_{N-1}, x_N]; x_0 = x-hat_{i|i}.
 // Constraints c_k = F(x_k, u_k) - x_{k+1} (F: RK4 with Nc steps over Ts,
 // u in mL/min); Lagrangian L = f - lambda^T c - pi_l^T (u - u_min)
 // - pi_u^T (u_max - u); f = phi of the Regulator section, stage costs on
-// x_1..x_N.
+// x_1..x_N.  Lane k holds u_k and the state after interval k, x_{k+1}
+// (value, multiplier of c_k, df/dx_{k+1}, its Hessian entry W_{x_{k+1}}),
+// and of the Hessian block {x_k, u_k} the entries W_{x_k u_k}, W_{u_k u_k}.
 #pragma once
 #include "mc_kernels.hpp"
 
+#ifndef MC_MS_WAVES_PER_EU
+#define MC_MS_WAVES_PER_EU 2   // wavefronts per SIMD the kernel is built for
+#endif
+
 namespace mccl {
 
-// Stage arrays.  Index k = 0..N-1 throughout; the state entries of stage k
-// are those of x_{k+1} (X, FX, WXX, DX, P, PV: the state after interval k).
-enum : int {
-    M_U = 0,   // u_k
-    M_X,       // x_{k+1}
-    M_LAM,     // lambda_k (constraint k)
-    M_PIL, M_PIU,
-    M_A, M_B,  // dF/dx, dF/du of interval k at (x_k, u_k)
-    M_C,       // c_k
-    M_FX,      // df/dx_{k+1}
-    M_WXX,     // Hessian block entry of x_{k+1}
-    M_WXU,     // off-diagonal entry of block {x_k, u_k} (k >= 1)
-    M_WUU,     // entry of u_k
-    M_SIG,     // merit weight sigma_k
-    M_DU, M_DX, M_MU, M_NL, M_NU,      // QP primal (du_k, dx_{k+1}) and dual
-    M_K, M_HI, M_P, M_KF, M_PV,        // Riccati: K_k, 1/H_uu,k, P_{k+1}, k_k, p_{k+1}
-    M_DUA,     // predictor (affine) du_k
-    M_COUNT
-};
-
 struct MsWork {
-    const int64_t* pos;
+    const int64_t* pos;  // sample positions, one per group
     int64_t n_pos;
     int n_groups;
-    int* queue;
-    const int* qhi;
-    double* ws;          // per slot: M_COUNT * NMAX * 64
-    int64_t stride;
+    int* queue;          // next group; starts at the chunk's first group
+    const int* qhi;      // end of the chunk's groups (device), or null: n_groups
 };
 
-// Stage-array accessor of one lane.
-template <int NMAX>
-struct MsArr {
-    double* base;   // slot base + lane
-    __device__ __forceinline__ double& operator()(int a, int k) const {
-        return base[((a * NMAX) + k) * 64];
+// --------------------------------------------------------- lane shifts ---
+// v of lane l - 1 (lane 0: `fill`) and of lane l + 1 (lanes >= n - 1:
+// `fill`).  Every lane must be active: a lane shift (ds_bpermute) reads
+// nothing from an inactive lane, so none sits inside a lane condition.
+__device__ __forceinline__ double lane_prev(double v, double fill) {
+    const double w = __shfl_up(v, 1, 64);
+    return threadIdx.x == 0 ? fill : w;
+}
+__device__ __forceinline__ double lane_next(double v, double fill, int n) {
+    const double w = __shfl_down(v, 1, 64);
+    return (int)threadIdx.x + 1 < n ? w : fill;
+}
+
+// Inclusive scans of affine maps f_k(x) = a_k x + b_k over lanes 0..span-1
+// (span a power of two).  Suffix: lane k ends with f_k o f_{k+1} o ...;
+// prefix: lane k ends with f_k o f_{k-1} o ... o f_0.  Lanes past the
+// stages hold the identity (1, 0).
+__device__ __forceinline__ void scan_affine_suffix(double& a, double& b, int span) {
+    const int lane = threadIdx.x;
+    for (int d = 1; d < span; d <<= 1) {
+        const double a2 = __shfl_down(a, d, 64), b2 = __shfl_down(b, d, 64);
+        if (lane + d < 64) {
+            b = fma(a, b2, b);
+            a = a * a2;
+        }
     }
+}
+__device__ __forceinline__ void scan_affine_prefix(double& a, double& b, int span) {
+    const int lane = threadIdx.x;
+    for (int d = 1; d < span; d <<= 1) {
+        const double a2 = __shfl_up(a, d, 64), b2 = __shfl_up(b, d, 64);
+        if (lane >= d) {
+            b = fma(a, b2, b);
+            a = a * a2;
+        }
+    }
+}
+
+// Linear-fractional maps P -> (m00 P + m01) / (m10 P + m11) as 2x2
+// matrices; a map is unchanged by a scale factor, so each matrix is
+// rescaled by a power of two (exact) to keep its entries near 1.
+struct Mob {
+    double m00, m01, m10, m11;
 };
+__device__ __forceinline__ Mob mob_norm(Mob m) {
+    const double mx = fmax(fmax(fabs(m.m00), fabs(m.m01)), fmax(fabs(m.m10), fabs(m.m11)));
+    int e = 0;
+    (void)frexp(mx, &e);
+    if (!(mx > 0.0) || !isfinite(mx)) e = 0;
+    return Mob{ldexp(m.m00, -e), ldexp(m.m01, -e), ldexp(m.m10, -e), ldexp(m.m11, -e)};
+}
+// Suffix scan: lane k ends with M_k M_{k+1} ... (matrix product; applied
+// to a vector, the rightmost map acts first).
+__device__ __forceinline__ Mob scan_mob_suffix(Mob m, int span) {
+    const int lane = threadIdx.x;
+    for (int d = 1; d < span; d <<= 1) {
+        const double p00 = __shfl_down(m.m00, d, 64), p01 = __shfl_down(m.m01, d, 64);
+        const double p10 = __shfl_down(m.m10, d, 64), p11 = __shfl_down(m.m11, d, 64);
+        if (lane + d < 64) {
+            m = mob_norm(Mob{fma(m.m00, p00, m.m01 * p10), fma(m.m00, p01, m.m01 * p11),
+                             fma(m.m10, p00, m.m11 * p10), fma(m.m10, p01, m.m11 * p11)});
+        }
+    }
+    return m;
+}
 
 // One sampling interval of the one-state model, RK4 with Nc steps: returns
 // F(x, u); with kDeriv also A = dF/dx, B = dF/du (u in mL/min) by the
@@ -128,6 +180,8 @@ __device__ __forceinline__ int ms_bfgs2(double& a, double& b, double& c, double 
     return 1;
 }
 
+
+
 // Structured QP, eq. (QP-subproblem), at the current SQP iterate:
 //   min 1/2 dxi^T W dxi + sum_k fx_k dx_{k+1}
 //   s.t. dx_{k+1} = A_k dx_k + B_k du_k + c_k (dx_0 = 0),
@@ -136,392 +190,335 @@ __device__ __forceinline__ int ms_bfgs2(double& a, double& b, double& c, double 
 // t_l = du - lo, t_u = hi - du kept positive, bound multipliers nu > 0,
 // fraction to the boundary 0.995 with separate primal and dual step
 // lengths.  Each Newton system is the equality-constrained stage QP with
-// R~_k = W_uu,k + nu_l/t_l + nu_u/t_u, solved by the backward Riccati
-// recursion (factor K_k, 1/H_uu,k, P_{k+1} once per iteration, shared by
-// predictor and corrector) and a forward sweep; the equality multipliers
-// follow as mu_k = -(P_{k+1} dx_{k+1} + p_{k+1}).  Start strictly inside the
-// box, 1e-2 of its width from the nearer bound, nu = 1, the states from the
-// dynamics.  Stop: stationarity residual <= 1e-12 (1 + |fx| + |W dxi|) and
-// mean complementarity <= 1e-14 (1 + |fx|) (infinity norms), or ipm_max_iter
-// iterations.  Returns 0 converged, 1 iteration cap, -1 an H_uu <= 0 (W not
-// positive definite).  Results in DU, DX, MU, NL, NU.
-// The stage arrays arrive as separate restrict-qualified pointers (element
-// k at [k * 64]): no store of one sweep can alias another array's load,
-// so the unrolled sweeps issue the loads of several stages together.
-__device__ __forceinline__ int ms_qp_body(const DevParams& p, int N, int& iters,
-                                         const double* __restrict__ gU,
-                                         const double* __restrict__ gA,
-                                         const double* __restrict__ gB,
-                                         const double* __restrict__ gC,
-                                         const double* __restrict__ gFX,
-                                         const double* __restrict__ gWXX,
-                                         const double* __restrict__ gWXU,
-                                         const double* __restrict__ gWUU,
-                                         double* __restrict__ gDU,
-                                         double* __restrict__ gDX,
-                                         double* __restrict__ gMU,
-                                         double* __restrict__ gNL,
-                                         double* __restrict__ gNU,
-                                         double* __restrict__ gK,
-                                         double* __restrict__ gHI,
-                                         double* __restrict__ gP,
-                                         double* __restrict__ gKF,
-                                         double* __restrict__ gPV,
-                                         double* __restrict__ gDUA) {
-    double gsc = 0.0;
+// R~_k = W_uu,k + nu_l/t_l + nu_u/t_u, solved by the Riccati recursion:
+// backwards P_N = W_{x_N}, H_uu,k = R~_k + B_k^2 P_{k+1},
+// H_ux,k = W_{x_k u_k} + B_k P_{k+1} A_k, K_k = -H_ux,k / H_uu,k,
+// P_k = W_{x_k} + A_k^2 P_{k+1} + H_ux,k K_k (the factor, shared by
+// predictor and corrector), the vector p_k = r_x,k + (A_k + B_k K_k) p_{k+1}
+// + K_k r~_u,k and k_k = -(r~_u,k + B_k p_{k+1}) / H_uu,k; forwards
+// du_k = K_k dx_k + k_k, dx_{k+1} = A_k dx_k + B_k du_k; the equality
+// multipliers follow as mu_k = -(P_{k+1} dx_{k+1} + p_{k+1}).  Eliminating
+// H_ux and H_uu, P_k = (alpha_k P_{k+1} + beta_k) / (B_k^2 P_{k+1} + R~_k)
+// with alpha_k = W_{x_k} B_k^2 + A_k^2 R~_k - 2 W_{x_k u_k} A_k B_k and
+// beta_k = W_{x_k} R~_k - W_{x_k u_k}^2 (both >= 0 for a positive definite
+// block), which the lanes compose by a scan (each map divided by R~_k).  Start strictly inside the
+// box, 1e-2 of its width from the nearer bound, nu = 1, the states from
+// the dynamics.  Stop: stationarity residual <= 1e-12 (1 + |fx| + |W dxi|)
+// and mean complementarity <= 1e-14 (1 + |fx|) (infinity norms), or
+// ipm_max_iter iterations.  Returns 0 converged, 1 iteration cap, -1 an
+// H_uu <= 0 (W not positive definite).  Lane k (k < N) passes its stage's
+// data and receives du_k, dx_{k+1}, mu_k and the bound multipliers; lanes
+// k >= N pass u = (u_min + u_max)/2, A = B = c = df/dx = 0 (no stage).
+struct MsStage {
+    double U, A, B, C, FX, WXX, WXU, WUU;
+};
+struct MsQpOut {
+    double du, dx, mu, nl, nu;
+};
+
+__device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, MsStage s,
+                                        MsQpOut& o, int& iters) {
+    const int lane = threadIdx.x;
+    const bool act = lane < N;
+    const bool hasx = act && lane >= 1;   // the stage has a state x_k in the NLP
+    const double lo = p.umin - s.U, hi = p.umax - s.U;
+    const double wxu = lane >= 1 ? s.WXU : 0.0;
+    const double wxp = lane_prev(s.WXX, 0.0);    // W_{x_k}
+    const double fxp = lane_prev(s.FX, 0.0);     // df/dx_k
+    const double PN = readlane_d(s.WXX, N - 1);  // W_{x_N}
+    const double fxN = readlane_d(s.FX, N - 1);
+    double du, nl = 1.0, nu = 1.0, mu = 0.0, dx;
     {
-        double dx = 0.0;
-        #pragma unroll 4
-        for (int k = 0; k < N; ++k) {
-            const double lo = p.umin - gU[(k) * 64], hi = p.umax - gU[(k) * 64];
-            const double dl = 1e-2 * (hi - lo);
-            double du = 0.0;
-            if (du < lo + dl) du = lo + dl;
-            if (du > hi - dl) du = hi - dl;
-            gDU[(k) * 64] = du;
-            gNL[(k) * 64] = 1.0;
-            gNU[(k) * 64] = 1.0;
-            gMU[(k) * 64] = 0.0;
-            dx = gA[(k) * 64] * dx + gB[(k) * 64] * du + gC[(k) * 64];
-            gDX[(k) * 64] = dx;
-            gsc = fmax(gsc, fabs(gFX[(k) * 64]));
-        }
+        const double dl = 1e-2 * (hi - lo);
+        du = 0.0;
+        if (du < lo + dl) du = lo + dl;
+        if (du > hi - dl) du = hi - dl;
+        double a = act ? s.A : 1.0, b = act ? fma(s.B, du, s.C) : 0.0;
+        scan_affine_prefix(a, b, span);
+        dx = b;   // dx_{k+1}; dx_0 = 0
     }
+    const double gsc = wave_max(act ? fabs(s.FX) : 0.0);
     const double inv2N = 1.0 / (2.0 * N);
     #pragma unroll 1
     for (int it = 0;; ++it) {
-        // backward sweep: residuals of the current point, their norms, the
-        // Riccati factors and the predictor's vectors (complementarity
-        // target 0)
-        double Pn = gWXX[(N - 1) * 64];
-        double rxN = gWXX[(N - 1) * 64] * gDX[(N - 1) * 64] + gFX[(N - 1) * 64] + gMU[(N - 1) * 64];
-        double pn = rxN;
-        double rmax = fabs(rxN), wd = fabs(gWXX[(N - 1) * 64] * gDX[(N - 1) * 64]), comp = 0.0;
-        #pragma unroll 4
-        for (int k = N - 1; k >= 0; --k) {
-            const double A = gA[(k) * 64], B = gB[(k) * 64];
-            const double du = gDU[(k) * 64], nl = gNL[(k) * 64], nu = gNU[(k) * 64], mu = gMU[(k) * 64];
-            const double dxk = k >= 1 ? gDX[(k - 1) * 64] : 0.0;
-            const double wuu = gWUU[(k) * 64], wxu = k >= 1 ? gWXU[(k) * 64] : 0.0;
-            const double lo = p.umin - gU[(k) * 64], hi = p.umax - gU[(k) * 64];
-            const double tl = du - lo, tu = hi - du;
-            const double wdu = wuu * du + wxu * dxk;
-            const double ru = wdu - mu * B - nl + nu;
-            comp += tl * nl + tu * nu;
-            const double Rt = wuu + nl / tl + nu / tu;
-            const double rt = ru + nl - nu;
-            const double e = pn;
-            const double Huu = Rt + B * B * Pn;
-            if (!(Huu > 0.0)) { iters = it; return -1; }
-            const double hinv = 1.0 / Huu;
-            const double kf = -(rt + B * e) * hinv;
-            gHI[(k) * 64] = hinv;
-            gKF[(k) * 64] = kf;
-            gP[(k) * 64] = Pn;
-            gPV[(k) * 64] = pn;
-            rmax = fmax(rmax, fabs(ru));
-            wd = fmax(wd, fabs(wdu));
-            if (k >= 1) {
-                const double wxx = gWXX[(k - 1) * 64];
-                const double wdx = wxx * dxk + wxu * du;
-                const double rx = wdx + gFX[(k - 1) * 64] - mu * A + gMU[(k - 1) * 64];
-                const double Hux = wxu + B * Pn * A;
-                const double K = -Hux * hinv;
-                gK[(k) * 64] = K;
-                Pn = wxx + A * A * Pn + Hux * K;
-                pn = rx + A * e + Hux * kf;
-                rmax = fmax(rmax, fabs(rx));
-                wd = fmax(wd, fabs(wdx));
-            }
+        // residuals of the current point
+        const double dxk = lane_prev(dx, 0.0);   // dx_k (dx_0 = 0)
+        const double mup = lane_prev(mu, 0.0);   // mu_{k-1}
+        const double tl = du - lo, tu = hi - du;
+        const double wdu = s.WUU * du + wxu * dxk;
+        const double ru = wdu - mu * s.B - nl + nu;
+        const double Rt = s.WUU + nl / tl + nu / tu;
+        const double rt = ru + nl - nu;
+        const double wdx = wxp * dxk + wxu * du;
+        const double rx = wdx + fxp - mu * s.A + mup;
+        const double dxN = readlane_d(dx, N - 1), muN = readlane_d(mu, N - 1);
+        const double rxN = PN * dxN + fxN + muN;
+        double rl = act ? fabs(ru) : 0.0, wl = act ? fabs(wdu) : 0.0;
+        if (hasx) {
+            rl = fmax(rl, fabs(rx));
+            wl = fmax(wl, fabs(wdx));
         }
+        const double rmax = fmax(fabs(rxN), wave_max(rl));
+        const double wd = fmax(fabs(PN * dxN), wave_max(wl));
+        const double comp = wave_sum(act ? tl * nl + tu * nu : 0.0);
+        // Riccati factor: lane k composes the maps of stages k+1..N-1
+        // (divided by R~_k: a slack that has reached 0 in floating point makes
+        // R~_k infinite, and the map tends to P -> A_k^2 P + W_{x_k})
+        Mob m{1.0, 0.0, 0.0, 1.0};
+        if (hasx) {
+            const double rR = 1.0 / Rt;
+            m = Mob{fma(s.A, s.A, (wxp * s.B * s.B - 2.0 * wxu * s.A * s.B) * rR), fma(-wxu * wxu, rR, wxp),
+                    s.B * s.B * rR, 1.0};
+        }
+        m = Mob{lane_next(m.m00, 1.0, N), lane_next(m.m01, 0.0, N), lane_next(m.m10, 0.0, N),
+                lane_next(m.m11, 1.0, N)};
+        m = scan_mob_suffix(mob_norm(m), span);
+        const double Pn = (m.m00 * PN + m.m01) / (m.m10 * PN + m.m11);   // P_{k+1}
+        const double Huu = Rt + s.B * s.B * Pn;
+        if (__ballot(act && !(Huu > 0.0))) {
+            iters = it;
+            return -1;
+        }
+        const double hinv = 1.0 / Huu;
+        const double K = -(wxu + s.B * Pn * s.A) * hinv;   // K_0 is not used
+        const double g = lane >= 1 ? fma(s.B, K, s.A) : 0.0;   // closed-loop gain of stage k
+        // predictor's Riccati vector: lane k composes p-maps of stages k+1..N-1
+        double va = hasx ? g : 1.0, vb = hasx ? fma(K, rt, rx) : 0.0;
+        va = lane_next(va, 1.0, N);
+        vb = lane_next(vb, 0.0, N);
+        scan_affine_suffix(va, vb, span);
+        const double e = fma(va, rxN, vb);      // p_{k+1}
+        const double kf = -(rt + s.B * e) * hinv;
         const double muc = comp * inv2N;
-        if (rmax <= 1e-12 * (1.0 + gsc + wd) && muc <= 1e-14 * (1.0 + gsc)) { iters = it; return 0; }
-        if (it == p.ipm_max_iter) { iters = it; return 1; }
+        if (rmax <= 1e-12 * (1.0 + gsc + wd) && muc <= 1e-14 * (1.0 + gsc)) {
+            iters = it;
+            o = MsQpOut{du, dx, mu, nl, nu};
+            return 0;
+        }
+        if (it == p.ipm_max_iter) {
+            iters = it;
+            o = MsQpOut{du, dx, mu, nl, nu};
+            return 1;
+        }
         // forward predictor: affine step and its lengths
-        double apr = 1.0, adr = 1.0;
-        {
-            double dx = 0.0;
-            #pragma unroll 4
-            for (int k = 0; k < N; ++k) {
-                const double dua = (k >= 1 ? gK[(k) * 64] * dx : 0.0) + gKF[(k) * 64];
-                gDUA[(k) * 64] = dua;
-                const double du = gDU[(k) * 64], nl = gNL[(k) * 64], nu = gNU[(k) * 64];
-                const double lo = p.umin - gU[(k) * 64], hi = p.umax - gU[(k) * 64];
-                const double tl = du - lo, tu = hi - du;
-                const double dnl = -nl - nl * dua / tl, dnu = -nu + nu * dua / tu;
-                if (dua < 0.0) apr = fmin(apr, -tl / dua);
-                if (dua > 0.0) apr = fmin(apr, tu / dua);
-                if (dnl < 0.0) adr = fmin(adr, -nl / dnl);
-                if (dnu < 0.0) adr = fmin(adr, -nu / dnu);
-                dx = gA[(k) * 64] * dx + gB[(k) * 64] * dua;
-            }
+        double fa = act ? g : 1.0, fb = act ? s.B * kf : 0.0;
+        scan_affine_prefix(fa, fb, span);
+        // (lane shifts run on the whole wavefront, outside any lane condition)
+        const double dxa = lane_prev(fb, 0.0);    // affine dx_k
+        const double dua = (lane >= 1 ? K * dxa : 0.0) + kf;
+        const double dnla = -nl - nl * dua / tl, dnua = -nu + nu * dua / tu;
+        double apl = 1.0, adl = 1.0;
+        if (act) {
+            if (dua < 0.0) apl = fmin(apl, -tl / dua);
+            if (dua > 0.0) apl = fmin(apl, tu / dua);
+            if (dnla < 0.0) adl = fmin(adl, -nl / dnla);
+            if (dnua < 0.0) adl = fmin(adl, -nu / dnua);
         }
-        double maff = 0.0;
-        #pragma unroll 4
-        for (int k = 0; k < N; ++k) {
-            const double dua = gDUA[(k) * 64];
-            const double du = gDU[(k) * 64], nl = gNL[(k) * 64], nu = gNU[(k) * 64];
-            const double lo = p.umin - gU[(k) * 64], hi = p.umax - gU[(k) * 64];
-            const double tl = du - lo, tu = hi - du;
-            const double dnl = -nl - nl * dua / tl, dnu = -nu + nu * dua / tu;
-            maff += (tl + apr * dua) * (nl + adr * dnl) + (tu - apr * dua) * (nu + adr * dnu);
-        }
-        maff *= inv2N;
+        const double apr = wave_min(apl), adr = wave_min(adl);
+        const double maff =
+            wave_sum(act ? (tl + apr * dua) * (nl + adr * dnla) + (tu - apr * dua) * (nu + adr * dnua)
+                         : 0.0) * inv2N;
         const double ratio = muc > 0.0 ? maff / muc : 0.0;
         const double smu = ratio * ratio * ratio * muc;   // sigma mu
-        // backward corrector: the Riccati vectors with the centred,
-        // second-order-corrected complementarity targets
-        pn = rxN;
-        #pragma unroll 4
-        for (int k = N - 1; k >= 0; --k) {
-            const double A = gA[(k) * 64], B = gB[(k) * 64];
-            const double du = gDU[(k) * 64], nl = gNL[(k) * 64], nu = gNU[(k) * 64], mu = gMU[(k) * 64];
-            const double dxk = k >= 1 ? gDX[(k - 1) * 64] : 0.0;
-            const double wuu = gWUU[(k) * 64], wxu = k >= 1 ? gWXU[(k) * 64] : 0.0;
-            const double lo = p.umin - gU[(k) * 64], hi = p.umax - gU[(k) * 64];
-            const double tl = du - lo, tu = hi - du;
-            const double ru = wuu * du + wxu * dxk - mu * B - nl + nu;
-            const double dua = gDUA[(k) * 64];
-            const double dnla = -nl - nl * dua / tl, dnua = -nu + nu * dua / tu;
-            const double taul = smu - dua * dnla, tauu = smu + dua * dnua;
-            const double rt = ru + nl - taul / tl - nu + tauu / tu;
-            const double Pn1 = gP[(k) * 64];
-            const double e = pn;
-            const double kf = -(rt + B * e) * gHI[(k) * 64];
-            gKF[(k) * 64] = kf;
-            gPV[(k) * 64] = pn;
-            if (k >= 1) {
-                const double wxx = gWXX[(k - 1) * 64];
-                const double rx = wxx * dxk + wxu * du + gFX[(k - 1) * 64] - mu * A + gMU[(k - 1) * 64];
-                const double Hux = wxu + B * Pn1 * A;
-                pn = rx + A * e + Hux * kf;
-            }
+        // corrector: the centred, second-order-corrected complementarity
+        // targets in the Riccati vector, then the forward steps
+        const double taul = smu - dua * dnla, tauu = smu + dua * dnua;
+        const double rt2 = ru + nl - taul / tl - nu + tauu / tu;
+        double ca = hasx ? g : 1.0, cb = hasx ? fma(K, rt2, rx) : 0.0;
+        ca = lane_next(ca, 1.0, N);
+        cb = lane_next(cb, 0.0, N);
+        scan_affine_suffix(ca, cb, span);
+        const double e2 = fma(ca, rxN, cb);     // p_{k+1}
+        const double kf2 = -(rt2 + s.B * e2) * hinv;
+        double ga = act ? g : 1.0, gb = act ? s.B * kf2 : 0.0;
+        scan_affine_prefix(ga, gb, span);
+        const double ddx = gb;                  // dx_{k+1} step
+        const double ddxk = lane_prev(gb, 0.0);
+        const double ddu = (lane >= 1 ? K * ddxk : 0.0) + kf2;
+        const double dmu = -(Pn * ddx + e2);
+        const double dnl = (-tl * nl + taul - nl * ddu) / tl;
+        const double dnu = (-tu * nu + tauu + nu * ddu) / tu;
+        double apl2 = 1.0, adl2 = 1.0;
+        if (act) {
+            if (ddu < 0.0) apl2 = fmin(apl2, -tl / ddu);
+            if (ddu > 0.0) apl2 = fmin(apl2, tu / ddu);
+            if (dnl < 0.0) adl2 = fmin(adl2, -nl / dnl);
+            if (dnu < 0.0) adl2 = fmin(adl2, -nu / dnu);
         }
-        // forward corrector, twice: step lengths, then the update with the
-        // direction recomputed (the same arithmetic, so the same values)
-        double ap = 1.0, ad = 1.0;
-        #pragma unroll 1
-        for (int pass = 0; pass < 2; ++pass) {
-            double dx = 0.0;
-            #pragma unroll 4
-            for (int k = 0; k < N; ++k) {
-                const double A = gA[(k) * 64], B = gB[(k) * 64];
-                const double ddu = (k >= 1 ? gK[(k) * 64] * dx : 0.0) + gKF[(k) * 64];
-                const double ddx = A * dx + B * ddu;
-                const double dmu = -(gP[(k) * 64] * ddx + gPV[(k) * 64]);
-                const double du = gDU[(k) * 64], nl = gNL[(k) * 64], nu = gNU[(k) * 64];
-                const double lo = p.umin - gU[(k) * 64], hi = p.umax - gU[(k) * 64];
-                const double tl = du - lo, tu = hi - du;
-                const double dua = gDUA[(k) * 64];
-                const double dnla = -nl - nl * dua / tl, dnua = -nu + nu * dua / tu;
-                const double taul = smu - dua * dnla, tauu = smu + dua * dnua;
-                const double dnl = (-tl * nl + taul - nl * ddu) / tl;
-                const double dnu = (-tu * nu + tauu + nu * ddu) / tu;
-                if (pass == 0) {
-                    if (ddu < 0.0) ap = fmin(ap, -tl / ddu);
-                    if (ddu > 0.0) ap = fmin(ap, tu / ddu);
-                    if (dnl < 0.0) ad = fmin(ad, -nl / dnl);
-                    if (dnu < 0.0) ad = fmin(ad, -nu / dnu);
-                } else {
-                    gDU[(k) * 64] = du + ap * ddu;
-                    gDX[(k) * 64] = gDX[(k) * 64] + ap * ddx;
-                    gMU[(k) * 64] = gMU[(k) * 64] + ad * dmu;
-                    gNL[(k) * 64] = nl + ad * dnl;
-                    gNU[(k) * 64] = nu + ad * dnu;
-                }
-                dx = ddx;
-            }
-            if (pass == 0) {
-                ap = fmin(1.0, 0.995 * ap);
-                ad = fmin(1.0, 0.995 * ad);
-            }
+        const double ap = fmin(1.0, 0.995 * wave_min(apl2));
+        const double ad = fmin(1.0, 0.995 * wave_min(adl2));
+        if (act) {
+            du = du + ap * ddu;
+            dx = dx + ap * ddx;
+            mu = mu + ad * dmu;
+            nl = nl + ad * dnl;
+            nu = nu + ad * dnu;
         }
     }
 }
 
-template <int NMAX>
-__device__ int ms_qp(const DevParams& p, const MsArr<NMAX>& a, int N, int& iters) {
-    auto g = [&](int m) { return &a(m, 0); };
-    return ms_qp_body(p, N, iters, g(M_U), g(M_A), g(M_B), g(M_C), g(M_FX), g(M_WXX), g(M_WXU), g(M_WUU), g(M_DU), g(M_DX), g(M_MU), g(M_NL), g(M_NU), g(M_K), g(M_HI), g(M_P), g(M_KF), g(M_PV), g(M_DUA));
-}
+// SQP state of one OCP, stage k on lane k.
+struct MsNlp {
+    double U, X, LAM, PIL, PIU, A, B, C, FX, WXX, WXU, WUU, SIG;
+};
 
-// Merit of the trial point xi + alpha dxi: f + sigma^T |c| (value-only
-// intervals).
-template <int NMAX>
-__device__ double ms_trial(const DevParams& p, const MsArr<NMAX>& a, int N, double x0, int i0,
-                           int istep, double sign, double alpha) {
-    double xk = x0, T = 0.0, dA, dB;
-    #pragma unroll 1
-    for (int k = 0; k < N; ++k) {
-        const double xn = a(M_X, k) + alpha * a(M_DX, k);
-        const double u = a(M_U, k) + alpha * a(M_DU, k);
-        const double F = ms_interval<false>(p, xk, u, dA, dB);
-        const double ez = xn / p.V - setpoint(p, i0 + 1 + k, istep, sign);
-        T += a(M_SIG, k) * fabs(F - xn) + p.Qz * p.Ts * ez * ez;
-        xk = xn;
-    }
-    return T;
-}
-
-// The SQP of one OCP from x-hat (x0) with the warm-started inputs in M_U;
+// The SQP of one OCP from x-hat (x0) with the warm-started inputs in U;
 // returns true if the KKT test passed (else the last iterate stands).
-template <int NMAX>
-__device__ bool ms_sqp(const DevParams& p, const MsArr<NMAX>& a, int N, double x0, int i0,
-                       int istep, double sign, int (&cnt)[C_NCNT]) {
+__device__ __forceinline__ bool ms_sqp_lanes(const DevParams& p, int N, int span, double x0,
+                                             int i0, int istep, double sign, double& Uio,
+                                             int (&cnt)[C_NCNT]) {
+    const int lane = threadIdx.x;
+    const bool act = lane < N;
     const double smax = 100.0;
     const double cst = 2.0 * p.Qz * p.Ts / p.V;
-    double f = 0.0;
+    const double qt = p.Qz * p.Ts;
+    const double zb = setpoint(p, i0 + 1 + lane, istep, sign);   // zbar of x_{k+1}
+    MsNlp v;
+    v.U = act ? Uio : 0.5 * (p.umin + p.umax);   // lanes past the stages: inside the box
+    if (v.U < p.umin) v.U = p.umin;
+    if (v.U > p.umax) v.U = p.umax;
     {
-        // feasible start: the states follow the inputs; W^[0] = I
-        double xk = x0;
-        #pragma unroll 4
+        // feasible start: the states follow the inputs, one stage after another
+        double xk = x0, X = 0.0;
+        #pragma unroll 1
         for (int k = 0; k < N; ++k) {
-            double u = a(M_U, k);
-            if (u < p.umin) u = p.umin;
-            if (u > p.umax) u = p.umax;
-            a(M_U, k) = u;
-            double A, B;
-            const double F = ms_interval<true>(p, xk, u, A, B);
-            a(M_A, k) = A;
-            a(M_B, k) = B;
-            a(M_X, k) = F;
-            a(M_C, k) = 0.0;
-            const double ez = F / p.V - setpoint(p, i0 + 1 + k, istep, sign);
-            a(M_FX, k) = cst * ez;
-            f += p.Qz * p.Ts * ez * ez;
-            a(M_WXX, k) = 1.0;
-            a(M_WXU, k) = 0.0;
-            a(M_WUU, k) = 1.0;
-            a(M_LAM, k) = 0.0;
-            a(M_PIL, k) = 0.0;
-            a(M_PIU, k) = 0.0;
-            a(M_SIG, k) = 0.0;
-            xk = F;
+            double dA, dB;
+            xk = ms_interval<false>(p, xk, readlane_d(v.U, k), dA, dB);
+            if (lane == k) X = xk;
         }
+        v.X = X;
     }
+    // interval tangents at (x_k, u_k), all stages at once
+    {
+        const double F = ms_interval<true>(p, lane_prev(v.X, x0), v.U, v.A, v.B);
+        v.C = F - v.X;
+    }
+    double f;
+    {
+        const double ez = v.X / p.V - zb;
+        v.FX = cst * ez;
+        f = wave_sum(act ? qt * ez * ez : 0.0);
+    }
+    if (!act) v.A = v.B = v.C = v.FX = 0.0;
+    v.WXX = 1.0;
+    v.WXU = 0.0;
+    v.WUU = 1.0;
+    v.LAM = v.PIL = v.PIU = v.SIG = 0.0;
     cnt[C_LS]++;
     cnt[C_GRAD]++;
     bool first = true;
     #pragma unroll 1
     for (int l = 0;; ++l) {
         // eq. (convergence): |grad L / s_d|_inf <= eps and |c|_inf <= eps
-        double s1 = 0.0, gmax = 0.0, cmax = 0.0;
-        bool bad = false;
-        #pragma unroll 4
-        for (int k = 0; k < N; ++k) {
-            const double lam = a(M_LAM, k), pl = a(M_PIL, k), pu = a(M_PIU, k);
-            s1 += fabs(lam) + fabs(pl) + fabs(pu);
-            const double gu = -lam * a(M_B, k) - pl + pu;
-            const double gx = a(M_FX, k) + lam - (k + 1 < N ? a(M_LAM, k + 1) * a(M_A, k + 1) : 0.0);
-            const double c = a(M_C, k);
-            bad = bad || !(gu == gu) || !(gx == gx) || !(c == c);
-            gmax = fmax(gmax, fmax(fabs(gu), fabs(gx)));
-            cmax = fmax(cmax, fabs(c));
-        }
+        const double s1 = wave_sum(act ? fabs(v.LAM) + fabs(v.PIL) + fabs(v.PIU) : 0.0);
+        const double gu = -v.LAM * v.B - v.PIL + v.PIU;
+        const double gx = v.FX + v.LAM - lane_next(v.LAM * v.A, 0.0, N);
+        const bool bad = __ballot(act && (!(gu == gu) || !(gx == gx) || !(v.C == v.C))) != 0;
+        const double gmax = wave_max(act ? fmax(fabs(gu), fabs(gx)) : 0.0);
+        const double cmax = wave_max(act ? fabs(v.C) : 0.0);
         const double sd = fmax(smax, s1 / (3.0 * N)) / smax;
-        if (!bad && gmax / sd <= p.sqp_eps && cmax <= p.sqp_eps) return true;
-        if (l == p.sqp_max_iter) return false;
-        // QP; an indefinite block (or H_uu <= 0 in the recursion) resets W
-        bool pd = true;
-        #pragma unroll 4
-        for (int k = 0; k < N; ++k) {
-            const double wuu = a(M_WUU, k), wxx = a(M_WXX, k);
-            pd = pd && wuu > 0.0 && wxx > 0.0;
-            if (k >= 1) {
-                const double wx = a(M_WXX, k - 1), wxu = a(M_WXU, k);
-                pd = pd && (wx * wuu - wxu * wxu > 0.0);
-            }
+        if (!bad && gmax / sd <= p.sqp_eps && cmax <= p.sqp_eps) {
+            Uio = v.U;
+            return true;
         }
-        int it = 0, st = pd ? ms_qp<NMAX>(p, a, N, it) : -1;
-        cnt[C_IPM] += it;
-        if (st == -1) {
-            cnt[C_RESET]++;
-            #pragma unroll 4
-            for (int k = 0; k < N; ++k) {
-                a(M_WXX, k) = 1.0;
-                a(M_WXU, k) = 0.0;
-                a(M_WUU, k) = 1.0;
+        if (l == p.sqp_max_iter) {
+            Uio = v.U;
+            return false;
+        }
+        // QP; an indefinite block (or H_uu <= 0 in the recursion) resets W
+        bool reset;
+        {
+            const double wxp = lane_prev(v.WXX, 1.0);
+            const bool pdl = v.WUU > 0.0 && v.WXX > 0.0 && (lane == 0 || wxp * v.WUU - v.WXU * v.WXU > 0.0);
+            reset = __ballot(act && !pdl) != 0;
+        }
+        MsQpOut q{0.0, 0.0, 0.0, 0.0, 0.0};
+        int st;
+        #pragma unroll 1
+        for (;;) {
+            if (reset) {
+                cnt[C_RESET]++;
+                v.WXX = 1.0;
+                v.WXU = 0.0;
+                v.WUU = 1.0;
             }
-            st = ms_qp<NMAX>(p, a, N, it);
+            int it = 0;
+            st = ms_qp_lanes(p, N, span, MsStage{v.U, v.A, v.B, v.C, v.FX, v.WXX, v.WXU, v.WUU}, q, it);
             cnt[C_IPM] += it;
+            if (st != -1 || reset) break;
+            reset = true;
         }
         if (st == 1) cnt[C_IPMCAP]++;
         cnt[C_SQP]++;
         // Powell's l1 merit: sigma = |mu| first, then max(|mu|, (sigma + |mu|)/2)
-        double T0 = f, D = 0.0;
-        #pragma unroll 4
-        for (int k = 0; k < N; ++k) {
-            const double am = fabs(a(M_MU, k));
-            const double sg = first ? am : fmax(am, 0.5 * (a(M_SIG, k) + am));
-            a(M_SIG, k) = sg;
-            const double ac = fabs(a(M_C, k));
-            T0 += sg * ac;
-            D += a(M_FX, k) * a(M_DX, k) - sg * ac;
+        {
+            const double am = fabs(q.mu);
+            v.SIG = first ? am : fmax(am, 0.5 * (v.SIG + am));
         }
         first = false;
+        const double ac = fabs(v.C);
+        const double T0 = f + wave_sum(act ? v.SIG * ac : 0.0);
+        const double D = wave_sum(act ? v.FX * q.dx - v.SIG * ac : 0.0);
         double alpha = 1.0;
         #pragma unroll 1
         for (int bt = 0;; ++bt) {
-            const double Tt = ms_trial<NMAX>(p, a, N, x0, i0, istep, sign, alpha);
+            // merit of the trial point xi + alpha dxi: f + sigma^T |c|
+            const double xn = v.X + alpha * q.dx;
+            const double u = v.U + alpha * q.du;
+            double dA, dB;
+            const double F = ms_interval<false>(p, lane_prev(xn, x0), u, dA, dB);
+            const double ez = xn / p.V - zb;
+            const double Tt = wave_sum(act ? v.SIG * fabs(F - xn) + qt * ez * ez : 0.0);
             cnt[C_LS]++;
             // a predicted decrease below the merit's resolution cannot be
             // tested in floating point: the full step is taken
             if (bt == 0 && -D <= 64.0 * 0x1p-52 * (1.0 + fabs(T0))) break;
             if (Tt <= T0 + p.ls_c1 * alpha * D) break;
-            if (bt == p.ls_max_bt) { cnt[C_LSCAP]++; break; }
+            if (bt == p.ls_max_bt) {
+                cnt[C_LSCAP]++;
+                break;
+            }
             alpha = p.ls_beta * alpha;
         }
-        // the step, the new interval derivatives, and the block BFGS with
+        // the step, the new interval tangents, and the block BFGS with
         // y = grad L(xi+, lambda+, pi+) - grad L(xi, lambda+, pi+)
-        f = 0.0;
+        const double su = alpha * q.du;
+        const double un = v.U + su;
+        const double sx = alpha * q.dx;           // step of x_{k+1}
+        const double xk1 = v.X + sx;
+        double An, Bn;
+        const double F = ms_interval<true>(p, lane_prev(xk1, x0), un, An, Bn);
+        const double lam = v.LAM + alpha * (q.mu - v.LAM);
+        v.LAM = lam;
+        v.PIL = v.PIL + alpha * (q.nl - v.PIL);
+        v.PIU = v.PIU + alpha * (q.nu - v.PIU);
+        const double ez = xk1 / p.V - zb;
+        const double fxn = cst * ez;
+        f = wave_sum(act ? qt * ez * ez : 0.0);
+        // block k = {x_k, u_k} on lane k (block 0 = {u_0}); block N = {x_N}
+        // on lane N - 1; W_{x_k} comes from lane k - 1 and goes back to it
+        double wa = lane_prev(v.WXX, 1.0);
+        const double sxk = lane_prev(sx, 0.0);
+        const double dfx = lane_prev(fxn - v.FX, 0.0);   // change of df/dx_k
         int applied = 0;
-        double xn = x0;              // x_k after the step
-        double fxo_k = 0.0, fxn_k = 0.0, sx_k = 0.0;   // df/dx_k old / new, alpha dx_k
-        #pragma unroll 1
-        for (int k = 0; k < N; ++k) {
-            const double Ao = a(M_A, k), Bo = a(M_B, k);
-            const double su = alpha * a(M_DU, k);
-            const double un = a(M_U, k) + su;
-            const double sxn = alpha * a(M_DX, k);
-            const double xk1 = a(M_X, k) + sxn;
-            double An, Bn;
-            const double F = ms_interval<true>(p, xn, un, An, Bn);
-            const double lam = a(M_LAM, k) + alpha * (a(M_MU, k) - a(M_LAM, k));
-            a(M_LAM, k) = lam;
-            a(M_PIL, k) = a(M_PIL, k) + alpha * (a(M_NL, k) - a(M_PIL, k));
-            a(M_PIU, k) = a(M_PIU, k) + alpha * (a(M_NU, k) - a(M_PIU, k));
-            const double ez = xk1 / p.V - setpoint(p, i0 + 1 + k, istep, sign);
-            const double fx_old = a(M_FX, k), fx_new = cst * ez;
-            f += p.Qz * p.Ts * ez * ez;
-            if (k == 0) {
-                double w = a(M_WUU, 0);
-                applied += ms_bfgs1(w, su, -lam * (Bn - Bo));
-                a(M_WUU, 0) = w;
-            } else {
-                double wa = a(M_WXX, k - 1), wb = a(M_WXU, k), wc = a(M_WUU, k);
-                applied += ms_bfgs2(wa, wb, wc, sx_k, su, fxn_k - fxo_k - lam * (An - Ao),
-                                    -lam * (Bn - Bo));
-                a(M_WXX, k - 1) = wa;
-                a(M_WXU, k) = wb;
-                a(M_WUU, k) = wc;
-            }
-            a(M_U, k) = un;
-            a(M_X, k) = xk1;
-            a(M_A, k) = An;
-            a(M_B, k) = Bn;
-            a(M_C, k) = F - xk1;
-            a(M_FX, k) = fx_new;
-            xn = xk1;
-            fxo_k = fx_old;
-            fxn_k = fx_new;
-            sx_k = sxn;
+        if (lane == 0) {
+            applied = ms_bfgs1(v.WUU, su, -lam * (Bn - v.B));
+        } else if (act) {
+            applied = ms_bfgs2(wa, v.WXU, v.WUU, sxk, su, dfx - lam * (An - v.A), -lam * (Bn - v.B));
         }
-        {
-            double w = a(M_WXX, N - 1);
-            applied += ms_bfgs1(w, sx_k, fxn_k - fxo_k);
-            a(M_WXX, N - 1) = w;
+        double wN = v.WXX;
+        if (lane == N - 1) applied |= ms_bfgs1(wN, sx, fxn - v.FX);
+        const double wnext = lane_next(wa, 0.0, N);
+        if (act) v.WXX = lane == N - 1 ? wN : wnext;
+        if (__ballot(act && applied) == 0) cnt[C_SKIP]++;
+        if (act) {
+            v.U = un;
+            v.X = xk1;
+            v.A = An;
+            v.B = Bn;
+            v.C = F - xk1;
+            v.FX = fxn;
         }
-        if (applied == 0) cnt[C_SKIP]++;
         cnt[C_GRAD]++;
     }
 }
@@ -547,76 +544,65 @@ __device__ __forceinline__ double ms_sample_flops(const DevParams& p, int N, int
     return fl;
 }
 
-// Persistent NMPC kernel of the multiple-shooting formulation: one sample
-// per lane, 64 per wavefront, groups taken from the work queue.  The
-// closed loop per interval is that of nmpc_kernel (cost, measurement, CD-EKF,
-// OCP, first input applied, Ns Euler-Maruyama sub-steps); the OCP starts
-// from the previous solution shifted by one interval with W^[0] = I.
-template <int NMAX>
-__global__ __launch_bounds__(64) void nmpc_ms_kernel(DevParams p, MsWork wk, Outs out) {
+
+// NMPC kernel of the multiple-shooting formulation: one sample per
+// wavefront (64-lane workgroup), groups of one sample taken from the work
+// queue.  The closed loop per interval is that of nmpc_kernel (cost,
+// measurement, CD-EKF, OCP, first input applied, Ns Euler-Maruyama
+// sub-steps); the plant and the estimator are the same on every lane, the
+// OCP runs a stage per lane.  Each OCP starts from the previous solution
+// shifted by one interval with W^[0] = I.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_MS_WAVES_PER_EU))) void nmpc_ms_kernel(DevParams p, MsWork wk, Outs out) {
     const int lane = threadIdx.x;
-    const MsArr<NMAX> a{wk.ws + (int64_t)blockIdx.x * wk.stride + lane};
     const double sqrtR = sqrt(p.Rmeas);
     const double h = p.Ts / (double)p.Ns;
     const double sqh = sqrt(h);
     const int g_hi = wk.qhi ? *wk.qhi : wk.n_groups;
+    #pragma unroll 1
     for (;;) {
         int grp = 0;
         if (lane == 0) grp = atomicAdd(wk.queue, 1);
-        grp = __shfl(grp, 0, 64);
+        grp = uni(__shfl(grp, 0, 64));
         if (grp >= g_hi) break;
-        const int64_t idx = (int64_t)grp * 64 + lane;
-        const bool has = idx < wk.n_pos;
-        const int64_t pos = has ? wk.pos[idx] : 0;
+        const int64_t pos = wk.pos[grp];
         const Setup su = sample_setup(p, pos);
-        const int N = has ? su.N : 1;
-        const int L = has ? su.L : -1;
+        const int N = uni(su.N);
+        const int L = uni(su.L);
+        int span = 1;
+        while (span < N) span <<= 1;
         int cnt[C_NCNT];
 #pragma unroll
         for (int c = 0; c < C_NCNT; ++c) cnt[c] = 0;
         double n[3] = {su.n0[0], su.n0[1], su.n0[2]};
         double xhat = su.xhat0, P = p.P0, Fprev = su.ubar, phiacc = 0.0;
         uint64_t hsh = 14695981039346656037ull;
-        if (has)
-            #pragma unroll 1
-            for (int k = 0; k < N; ++k) a(M_U, k) = su.ubar * kMlMinPerLs;
-        const int Lmax = wave_max_i(L);
-        int Lrun = L;   // cut short when the plant state stops being finite
-        for (int i = 0; i <= Lmax; ++i) {
-            const bool live = has && i <= Lrun;
-            const bool step = live && i < Lrun;
-            if (!live) continue;
+        double U = su.ubar * kMlMinPerLs;   // u_k of the warm start on lane k
+        #pragma unroll 1
+        for (int i = 0; i <= L; ++i) {
             const double z = n[2] / p.V;
             const double zb = setpoint(p, i, su.istep, su.sign);
             phiacc += (z - zb) * (z - zb);
-            if (out.tz) out.tz[(int64_t)i * out.S + pos] = z;
+            if (out.tz && lane == 0) out.tz[(int64_t)i * out.S + pos] = z;
             if (!isfinite(z)) {
                 // the plant diverged (Phi is not a number): no more OCPs
                 cnt[C_NONFIN] = 1;
-                Lrun = i;
-                continue;
+                break;
             }
-            if (!step) continue;
+            if (i == L) break;
             const double y = z + p.noise_scale * sqrtR *
                                      normal_first(p.seed, 0, (uint32_t)i, su.nid, kTagMeas);
             ekf_predict(p, xhat, P, Fprev);
             ekf_update(p, xhat, P, y);
             if (!isfinite(P) || !isfinite(xhat)) cnt[C_NONFIN] = 1;
-            if (out.tx) out.tx[(int64_t)i * out.S + pos] = xhat;
-            const bool conv = ms_sqp<NMAX>(p, a, N, xhat, i, su.istep, su.sign, cnt);
+            if (out.tx && lane == 0) out.tx[(int64_t)i * out.S + pos] = xhat;
+            const bool conv = ms_sqp_lanes(p, N, span, xhat, i, su.istep, su.sign, U, cnt);
             cnt[C_OCP]++;
             if (!conv) cnt[C_OCP_FAIL]++;
-            uint64_t mask = 0;
-            #pragma unroll 4
-            for (int k = 0; k < N; ++k) {
-                const double v = a(M_U, k);
-                if (v <= p.umin + 1e-6 || v >= p.umax - 1e-6) mask |= (1ull << k);
-            }
+            const uint64_t mask = __ballot(lane < N && (U <= p.umin + 1e-6 || U >= p.umax - 1e-6));
             hsh = fnv1a_step(hsh, (uint32_t)i, mask);
-            const double F = a(M_U, 0) / kMlMinPerLs;
-            #pragma unroll 4
-            for (int k = 0; k + 1 < N; ++k) a(M_U, k) = a(M_U, k + 1);
-            if (out.tu) out.tu[(int64_t)i * out.S + pos] = F;
+            const double F = readlane_d(U, 0) / kMlMinPerLs;
+            U = lane_next(U, U, N);   // shift: u_k <- u_{k+1}, the last one kept
+            if (out.tu && lane == 0) out.tu[(int64_t)i * out.S + pos] = F;
             #pragma unroll 1
             for (int j = 0; j < p.Ns; ++j) {
                 double xi[3];
@@ -625,8 +611,8 @@ __global__ __launch_bounds__(64) void nmpc_ms_kernel(DevParams p, MsWork wk, Out
             }
             Fprev = F;
         }
-        if (has) {
-            if (!isfinite(n[0]) || !isfinite(n[1]) || !isfinite(n[2])) cnt[C_NONFIN] = 1;
+        if (!isfinite(n[0]) || !isfinite(n[1]) || !isfinite(n[2])) cnt[C_NONFIN] = 1;
+        if (lane == 0) {
             out.phi[pos] = phiacc / (double)(L + 1);
             out.hash[pos] = hsh;
             cnt[C_KIND] = 0;
