@@ -54,41 +54,87 @@ struct MsWork {
 };
 
 // --------------------------------------------------------- lane shifts ---
+// Data-parallel primitives (DPP) move values between lanes inside the VALU,
+// with no LDS round trip.  Every lane must be active: none of these sits
+// inside a lane condition.
 // v of lane l - 1 (lane 0: `fill`) and of lane l + 1 (lanes >= n - 1:
-// `fill`).  Every lane must be active: a lane shift (ds_bpermute) reads
-// nothing from an inactive lane, so none sits inside a lane condition.
+// `fill`): the wavefront shifts by one lane.
 __device__ __forceinline__ double lane_prev(double v, double fill) {
-    const double w = __shfl_up(v, 1, 64);
-    return threadIdx.x == 0 ? fill : w;
+    return dpp_d<0x138, 0xf>(fill, v);   // wave_shr:1
 }
 __device__ __forceinline__ double lane_next(double v, double fill, int n) {
-    const double w = __shfl_down(v, 1, 64);
+    const double w = dpp_d<0x130, 0xf>(fill, v);   // wave_shl:1
     return (int)threadIdx.x + 1 < n ? w : fill;
 }
 
-// Inclusive scans of affine maps f_k(x) = a_k x + b_k over lanes 0..span-1
-// (span a power of two).  Suffix: lane k ends with f_k o f_{k+1} o ...;
-// prefix: lane k ends with f_k o f_{k-1} o ... o f_0.  Lanes past the
-// stages hold the identity (1, 0).
-__device__ __forceinline__ void scan_affine_suffix(double& a, double& b, int span) {
-    const int lane = threadIdx.x;
-    for (int d = 1; d < span; d <<= 1) {
-        const double a2 = __shfl_down(a, d, 64), b2 = __shfl_down(b, d, 64);
-        if (lane + d < 64) {
-            b = fma(a, b2, b);
-            a = a * a2;
+// Inclusive scans over lanes 0..span-1 (span a power of two, <= 64) of
+// maps composed by `after(f, g)` = f o g.  Prefix: lane k ends with
+// f_k o f_{k-1} o ... o f_0; suffix: lane k ends with f_k o f_{k+1} o ....
+// Within each 16-lane row the scan takes row shifts by 1, 2, 4 and 8
+// (lanes without a source in the row compose with the identity `id`).
+// Across rows, a prefix takes the row broadcasts of lanes 15 and 31; a
+// suffix reads the row totals (lanes 16, 32, 48) and composes each row
+// with the totals of the rows after it.
+template <class T>
+struct DppOps;
+template <class T, class After>
+__device__ __forceinline__ T scan_prefix(T f, T id, int span, After after) {
+    f = after(f, DppOps<T>::template mov<0x111, 0xf>(id, f));      // row_shr:1
+    if (span > 2) f = after(f, DppOps<T>::template mov<0x112, 0xf>(id, f));
+    if (span > 4) f = after(f, DppOps<T>::template mov<0x114, 0xf>(id, f));
+    if (span > 8) f = after(f, DppOps<T>::template mov<0x118, 0xf>(id, f));
+    if (span > 16) f = after(f, DppOps<T>::template mov<0x142, 0xa>(id, f));   // row_bcast:15
+    if (span > 32) f = after(f, DppOps<T>::template mov<0x143, 0xc>(id, f));   // row_bcast:31
+    return f;
+}
+template <class T, class After>
+__device__ __forceinline__ T scan_suffix(T f, T id, int span, After after) {
+    f = after(f, DppOps<T>::template mov<0x101, 0xf>(id, f));      // row_shl:1
+    if (span > 2) f = after(f, DppOps<T>::template mov<0x102, 0xf>(id, f));
+    if (span > 4) f = after(f, DppOps<T>::template mov<0x104, 0xf>(id, f));
+    if (span > 8) f = after(f, DppOps<T>::template mov<0x108, 0xf>(id, f));
+    if (span > 16) {
+        const int row = threadIdx.x >> 4;
+        const T t1 = DppOps<T>::readlane(f, 16);
+        T s = t1;   // rows after row 0 (of 2)
+        if (span > 32) {
+            const T t3 = DppOps<T>::readlane(f, 48);
+            const T s2 = after(DppOps<T>::readlane(f, 32), t3);   // rows 2..3
+            s = row == 0 ? after(t1, s2) : row == 1 ? s2 : row == 2 ? t3 : id;
+        } else {
+            s = row == 0 ? t1 : id;
         }
+        f = after(f, s);
     }
+    return f;
+}
+
+// Affine maps x -> a x + b.
+struct Aff {
+    double a, b;
+};
+template <>
+struct DppOps<Aff> {
+    template <int CTRL, int ROWMASK>
+    __device__ static __forceinline__ Aff mov(Aff old, Aff v) {
+        return Aff{dpp_d<CTRL, ROWMASK>(old.a, v.a), dpp_d<CTRL, ROWMASK>(old.b, v.b)};
+    }
+    __device__ static __forceinline__ Aff readlane(Aff v, int l) {
+        return Aff{readlane_d(v.a, l), readlane_d(v.b, l)};
+    }
+};
+__device__ __forceinline__ Aff aff_after(Aff f, Aff g) {
+    return Aff{f.a * g.a, fma(f.a, g.b, f.b)};
+}
+__device__ __forceinline__ void scan_affine_suffix(double& a, double& b, int span) {
+    const Aff r = scan_suffix(Aff{a, b}, Aff{1.0, 0.0}, span, aff_after);
+    a = r.a;
+    b = r.b;
 }
 __device__ __forceinline__ void scan_affine_prefix(double& a, double& b, int span) {
-    const int lane = threadIdx.x;
-    for (int d = 1; d < span; d <<= 1) {
-        const double a2 = __shfl_up(a, d, 64), b2 = __shfl_up(b, d, 64);
-        if (lane >= d) {
-            b = fma(a, b2, b);
-            a = a * a2;
-        }
-    }
+    const Aff r = scan_prefix(Aff{a, b}, Aff{1.0, 0.0}, span, aff_after);
+    a = r.a;
+    b = r.b;
 }
 
 // Linear-fractional maps P -> (m00 P + m01) / (m10 P + m11) as 2x2
@@ -104,19 +150,25 @@ __device__ __forceinline__ Mob mob_norm(Mob m) {
     if (!(mx > 0.0) || !isfinite(mx)) e = 0;
     return Mob{ldexp(m.m00, -e), ldexp(m.m01, -e), ldexp(m.m10, -e), ldexp(m.m11, -e)};
 }
-// Suffix scan: lane k ends with M_k M_{k+1} ... (matrix product; applied
-// to a vector, the rightmost map acts first).
-__device__ __forceinline__ Mob scan_mob_suffix(Mob m, int span) {
-    const int lane = threadIdx.x;
-    for (int d = 1; d < span; d <<= 1) {
-        const double p00 = __shfl_down(m.m00, d, 64), p01 = __shfl_down(m.m01, d, 64);
-        const double p10 = __shfl_down(m.m10, d, 64), p11 = __shfl_down(m.m11, d, 64);
-        if (lane + d < 64) {
-            m = mob_norm(Mob{fma(m.m00, p00, m.m01 * p10), fma(m.m00, p01, m.m01 * p11),
-                             fma(m.m10, p00, m.m11 * p10), fma(m.m10, p01, m.m11 * p11)});
-        }
+template <>
+struct DppOps<Mob> {
+    template <int CTRL, int ROWMASK>
+    __device__ static __forceinline__ Mob mov(Mob old, Mob v) {
+        return Mob{dpp_d<CTRL, ROWMASK>(old.m00, v.m00), dpp_d<CTRL, ROWMASK>(old.m01, v.m01),
+                   dpp_d<CTRL, ROWMASK>(old.m10, v.m10), dpp_d<CTRL, ROWMASK>(old.m11, v.m11)};
     }
-    return m;
+    __device__ static __forceinline__ Mob readlane(Mob v, int l) {
+        return Mob{readlane_d(v.m00, l), readlane_d(v.m01, l), readlane_d(v.m10, l), readlane_d(v.m11, l)};
+    }
+};
+// m o g as the matrix product m g (applied to a vector, g acts first).
+__device__ __forceinline__ Mob mob_after(Mob m, Mob g) {
+    return mob_norm(Mob{fma(m.m00, g.m00, m.m01 * g.m10), fma(m.m00, g.m01, m.m01 * g.m11),
+                        fma(m.m10, g.m00, m.m11 * g.m10), fma(m.m10, g.m01, m.m11 * g.m11)});
+}
+// Suffix scan: lane k ends with M_k M_{k+1} ....
+__device__ __forceinline__ Mob scan_mob_suffix(Mob m, int span) {
+    return scan_suffix(m, Mob{1.0, 0.0, 0.0, 1.0}, span, mob_after);
 }
 
 // One sampling interval of the one-state model, RK4 with Nc steps: returns
@@ -179,8 +231,6 @@ __device__ __forceinline__ int ms_bfgs2(double& a, double& b, double& c, double 
     c = c - w2 * w2 / sWs + r2 * r2 / sr;
     return 1;
 }
-
-
 
 // Structured QP, eq. (QP-subproblem), at the current SQP iterate:
 //   min 1/2 dxi^T W dxi + sum_k fx_k dx_{k+1}
