@@ -357,9 +357,10 @@ def nmpc_subset_run(cfg, n, stride=1, **over):
 
 def side_runs(cfg):
     """Paper-scale side measurements: the whole campaign's NMPC half at
-    eps = 1e-8; the paper's W^[0] = I at every OCP with single shooting and
-    with the paper's multiple-shooting NLP, on strided NMPC subsets beside
-    the default single shooting with the shifted Hessian."""
+    eps = 1e-8, and with the paper's multiple-shooting NLP; the paper's
+    W^[0] = I at every OCP with single shooting and with the
+    multiple-shooting NLP, on strided NMPC subsets beside the default single
+    shooting with the shifted Hessian; a Monte Carlo tuning sweep."""
     import numpy as np
     import torch
 
@@ -383,6 +384,27 @@ def side_runs(cfg):
                            sqp_iter_per_ocp=round(tot["sqp_iter"] / max(1, tot["n_ocp"]), 3))
     camp.close()
     log(f"eps 1e-8: {res['eps_1e-8']}")
+    # the paper's own NLP (multiple shooting, W^[0] = I) on the whole campaign
+    cm = dict(cfg, nlp_form=1)
+    camp = binding.Campaign(cm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    camp.run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    _, st = camp.costs()
+    tot = st["totals"]
+    n_nm = cm["n_samples"] - tot["kind"]
+    km = camp.kernel_ms()[0]
+    tf = st["flops_by_kind"][0] / km / 1e9
+    res["multiple_shooting_full"] = dict(
+        nmpc_sims_per_s=round(n_nm / dt, 3), ms_per_step=round(dt * 1e3, 3),
+        nmpc_kernel_ms=round(km, 3), ocp_total=tot["n_ocp"], ocp_failed=tot["n_ocp_fail"],
+        sqp_iter_per_ocp=round(tot["sqp_iter"] / max(1, tot["n_ocp"]), 3),
+        ipm_iter_per_sqp=round(tot["ipm_iter"] / max(1, tot["sqp_iter"]), 3),
+        mean_phi_nmpc=st["mean"][0], algorithmic_tflops=round(tf, 4), frac_fp64_peak=round(tf / 78.6, 5))
+    camp.close()
+    log(f"multiple shooting, whole campaign: {res['multiple_shooting_full']}")
     n, stride = 1024, 29
     base, phi0 = nmpc_subset_run(cfg, n, stride)
     lit, phi1 = nmpc_subset_run(cfg, n, stride, hess_warm=0)

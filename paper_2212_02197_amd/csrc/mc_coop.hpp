@@ -54,12 +54,22 @@ __device__ __forceinline__ double dpp_d(double old, double v) {
                                                0xf, false);
     return __hiloint2double(hi, lo);
 }
+// v moved by a DPP control on every row and bank, lanes without a source
+// reading 0 (bound_ctrl): no earlier value of the destination survives, so
+// none has to be set up (quad permutations and row rotations have a source
+// on every lane).
+template <int CTRL>
+__device__ __forceinline__ double dpp_z(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
 template <typename Op>
 __device__ __forceinline__ double wave_reduce(double v, double id, Op op) {
-    v = op(v, dpp_d<0xB1, 0xf>(id, v));    // quad_perm [1,0,3,2]
-    v = op(v, dpp_d<0x4E, 0xf>(id, v));    // quad_perm [2,3,0,1]
-    v = op(v, dpp_d<0x124, 0xf>(id, v));   // row_ror:4
-    v = op(v, dpp_d<0x128, 0xf>(id, v));   // row_ror:8
+    v = op(v, dpp_z<0xB1>(v));    // quad_perm [1,0,3,2]
+    v = op(v, dpp_z<0x4E>(v));    // quad_perm [2,3,0,1]
+    v = op(v, dpp_z<0x124>(v));   // row_ror:4
+    v = op(v, dpp_z<0x128>(v));   // row_ror:8
     v = op(v, dpp_d<0x142, 0xa>(id, v));   // row_bcast:15 into rows 1, 3
     v = op(v, dpp_d<0x143, 0xc>(id, v));   // row_bcast:31 into rows 2, 3
     return readlane_d(v, 63);

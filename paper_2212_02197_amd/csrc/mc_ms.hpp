@@ -57,42 +57,57 @@ struct MsWork {
 // Data-parallel primitives (DPP) move values between lanes inside the VALU,
 // with no LDS round trip.  Every lane must be active: none of these sits
 // inside a lane condition.
-// v of lane l - 1 (lane 0: `fill`) and of lane l + 1 (lanes >= n - 1:
+// v of lane l - 1 (lane 0: `fill`, or 0) and of lane l + 1 (lanes >= n - 1:
 // `fill`): the wavefront shifts by one lane.
+__device__ __forceinline__ double lane_prev(double v) {
+    return dpp_z<0x138>(v);   // wave_shr:1
+}
 __device__ __forceinline__ double lane_prev(double v, double fill) {
-    return dpp_d<0x138, 0xf>(fill, v);   // wave_shr:1
+    return dpp_d<0x138, 0xf>(fill, v);
 }
 __device__ __forceinline__ double lane_next(double v, double fill, int n) {
-    const double w = dpp_d<0x130, 0xf>(fill, v);   // wave_shl:1
+    const double w = dpp_z<0x130>(v);   // wave_shl:1
     return (int)threadIdx.x + 1 < n ? w : fill;
+}
+// A row shift by d (CTRL) of v with bound_ctrl: lanes without a source in
+// the row read `one` when it is set, else 0 (only the high word of 1.0 is
+// not 0).
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double v, bool has_src, bool one) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+    int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
+    if (one) hi = has_src ? hi : 0x3ff00000;
+    return __hiloint2double(hi, lo);
 }
 
 // Inclusive scans over lanes 0..span-1 (span a power of two, <= 64) of
 // maps composed by `after(f, g)` = f o g.  Prefix: lane k ends with
 // f_k o f_{k-1} o ... o f_0; suffix: lane k ends with f_k o f_{k+1} o ....
 // Within each 16-lane row the scan takes row shifts by 1, 2, 4 and 8
-// (lanes without a source in the row compose with the identity `id`).
-// Across rows, a prefix takes the row broadcasts of lanes 15 and 31; a
-// suffix reads the row totals (lanes 16, 32, 48) and composes each row
-// with the totals of the rows after it.
+// (lanes without a source in the row compose with the identity).  Across
+// rows, a prefix takes the row broadcasts of lanes 15 and 31; a suffix
+// reads the row totals (lanes 16, 32, 48) and composes each row with the
+// totals of the rows after it.
 template <class T>
 struct DppOps;
 template <class T, class After>
 __device__ __forceinline__ T scan_prefix(T f, T id, int span, After after) {
-    f = after(f, DppOps<T>::template mov<0x111, 0xf>(id, f));      // row_shr:1
-    if (span > 2) f = after(f, DppOps<T>::template mov<0x112, 0xf>(id, f));
-    if (span > 4) f = after(f, DppOps<T>::template mov<0x114, 0xf>(id, f));
-    if (span > 8) f = after(f, DppOps<T>::template mov<0x118, 0xf>(id, f));
+    const int r = threadIdx.x & 15;
+    f = after(f, DppOps<T>::template row<0x111>(f, r >= 1));      // row_shr:1
+    if (span > 2) f = after(f, DppOps<T>::template row<0x112>(f, r >= 2));
+    if (span > 4) f = after(f, DppOps<T>::template row<0x114>(f, r >= 4));
+    if (span > 8) f = after(f, DppOps<T>::template row<0x118>(f, r >= 8));
     if (span > 16) f = after(f, DppOps<T>::template mov<0x142, 0xa>(id, f));   // row_bcast:15
     if (span > 32) f = after(f, DppOps<T>::template mov<0x143, 0xc>(id, f));   // row_bcast:31
     return f;
 }
 template <class T, class After>
 __device__ __forceinline__ T scan_suffix(T f, T id, int span, After after) {
-    f = after(f, DppOps<T>::template mov<0x101, 0xf>(id, f));      // row_shl:1
-    if (span > 2) f = after(f, DppOps<T>::template mov<0x102, 0xf>(id, f));
-    if (span > 4) f = after(f, DppOps<T>::template mov<0x104, 0xf>(id, f));
-    if (span > 8) f = after(f, DppOps<T>::template mov<0x108, 0xf>(id, f));
+    const int r = threadIdx.x & 15;
+    f = after(f, DppOps<T>::template row<0x101>(f, r <= 14));      // row_shl:1
+    if (span > 2) f = after(f, DppOps<T>::template row<0x102>(f, r <= 13));
+    if (span > 4) f = after(f, DppOps<T>::template row<0x104>(f, r <= 11));
+    if (span > 8) f = after(f, DppOps<T>::template row<0x108>(f, r <= 7));
     if (span > 16) {
         const int row = threadIdx.x >> 4;
         const T t1 = DppOps<T>::readlane(f, 16);
@@ -118,6 +133,10 @@ struct DppOps<Aff> {
     template <int CTRL, int ROWMASK>
     __device__ static __forceinline__ Aff mov(Aff old, Aff v) {
         return Aff{dpp_d<CTRL, ROWMASK>(old.a, v.a), dpp_d<CTRL, ROWMASK>(old.b, v.b)};
+    }
+    template <int CTRL>
+    __device__ static __forceinline__ Aff row(Aff v, bool has_src) {
+        return Aff{dpp_row<CTRL>(v.a, has_src, true), dpp_row<CTRL>(v.b, has_src, false)};
     }
     __device__ static __forceinline__ Aff readlane(Aff v, int l) {
         return Aff{readlane_d(v.a, l), readlane_d(v.b, l)};
@@ -157,18 +176,50 @@ struct DppOps<Mob> {
         return Mob{dpp_d<CTRL, ROWMASK>(old.m00, v.m00), dpp_d<CTRL, ROWMASK>(old.m01, v.m01),
                    dpp_d<CTRL, ROWMASK>(old.m10, v.m10), dpp_d<CTRL, ROWMASK>(old.m11, v.m11)};
     }
+    template <int CTRL>
+    __device__ static __forceinline__ Mob row(Mob v, bool has_src) {
+        return Mob{dpp_row<CTRL>(v.m00, has_src, true), dpp_row<CTRL>(v.m01, has_src, false),
+                   dpp_row<CTRL>(v.m10, has_src, false), dpp_row<CTRL>(v.m11, has_src, true)};
+    }
     __device__ static __forceinline__ Mob readlane(Mob v, int l) {
         return Mob{readlane_d(v.m00, l), readlane_d(v.m01, l), readlane_d(v.m10, l), readlane_d(v.m11, l)};
     }
 };
-// m o g as the matrix product m g (applied to a vector, g acts first).
+// m o g as the matrix product m g (applied to a vector, g acts first); the
+// scan rescales after every second product (the entries of two products of
+// rescaled matrices stay far inside the FP64 range).
+__device__ __forceinline__ Mob mob_mul(Mob m, Mob g) {
+    return Mob{fma(m.m00, g.m00, m.m01 * g.m10), fma(m.m00, g.m01, m.m01 * g.m11),
+               fma(m.m10, g.m00, m.m11 * g.m10), fma(m.m10, g.m01, m.m11 * g.m11)};
+}
 __device__ __forceinline__ Mob mob_after(Mob m, Mob g) {
-    return mob_norm(Mob{fma(m.m00, g.m00, m.m01 * g.m10), fma(m.m00, g.m01, m.m01 * g.m11),
-                        fma(m.m10, g.m00, m.m11 * g.m10), fma(m.m10, g.m01, m.m11 * g.m11)});
+    return mob_norm(mob_mul(m, g));
+}
+__device__ __forceinline__ Mob mob_after_raw(Mob m, Mob g) {
+    return mob_mul(m, g);
 }
 // Suffix scan: lane k ends with M_k M_{k+1} ....
 __device__ __forceinline__ Mob scan_mob_suffix(Mob m, int span) {
-    return scan_suffix(m, Mob{1.0, 0.0, 0.0, 1.0}, span, mob_after);
+    const Mob id{1.0, 0.0, 0.0, 1.0};
+    const int r = threadIdx.x & 15;
+    m = mob_after_raw(m, DppOps<Mob>::row<0x101>(m, r <= 14));      // row_shl:1
+    if (span > 2) m = mob_after(m, DppOps<Mob>::row<0x102>(m, r <= 13));
+    if (span > 4) m = mob_after_raw(m, DppOps<Mob>::row<0x104>(m, r <= 11));
+    if (span > 8) m = mob_after(m, DppOps<Mob>::row<0x108>(m, r <= 7));
+    if (span > 16) {
+        const int row = threadIdx.x >> 4;
+        const Mob t1 = DppOps<Mob>::readlane(m, 16);
+        Mob s = t1;
+        if (span > 32) {
+            const Mob t3 = DppOps<Mob>::readlane(m, 48);
+            const Mob s2 = mob_after(DppOps<Mob>::readlane(m, 32), t3);
+            s = row == 0 ? mob_after(t1, s2) : row == 1 ? s2 : row == 2 ? t3 : id;
+        } else {
+            s = row == 0 ? t1 : id;
+        }
+        m = mob_after(m, s);
+    }
+    return m;
 }
 
 // One sampling interval of the one-state model, RK4 with Nc steps: returns
@@ -232,6 +283,17 @@ __device__ __forceinline__ int ms_bfgs2(double& a, double& b, double& c, double 
     return 1;
 }
 
+// 1/a for finite nonzero a: the hardware estimate and two Newton steps
+// (each doubles the correct bits; within an ulp or two of the quotient).
+// Where a may be 0 or infinite the interior point divides instead.
+__device__ __forceinline__ double rcp_nr(double a) {
+    double y = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-a, y, 1.0);
+    return fma(y, e, y);
+}
+
 // Structured QP, eq. (QP-subproblem), at the current SQP iterate:
 //   min 1/2 dxi^T W dxi + sum_k fx_k dx_{k+1}
 //   s.t. dx_{k+1} = A_k dx_k + B_k du_k + c_k (dx_0 = 0),
@@ -273,8 +335,8 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
     const bool hasx = act && lane >= 1;   // the stage has a state x_k in the NLP
     const double lo = p.umin - s.U, hi = p.umax - s.U;
     const double wxu = lane >= 1 ? s.WXU : 0.0;
-    const double wxp = lane_prev(s.WXX, 0.0);    // W_{x_k}
-    const double fxp = lane_prev(s.FX, 0.0);     // df/dx_k
+    const double wxp = lane_prev(s.WXX);    // W_{x_k}
+    const double fxp = lane_prev(s.FX);     // df/dx_k
     const double PN = readlane_d(s.WXX, N - 1);  // W_{x_N}
     const double fxN = readlane_d(s.FX, N - 1);
     double du, nl = 1.0, nu = 1.0, mu = 0.0, dx;
@@ -292,12 +354,13 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
     #pragma unroll 1
     for (int it = 0;; ++it) {
         // residuals of the current point
-        const double dxk = lane_prev(dx, 0.0);   // dx_k (dx_0 = 0)
-        const double mup = lane_prev(mu, 0.0);   // mu_{k-1}
+        const double dxk = lane_prev(dx);   // dx_k (dx_0 = 0)
+        const double mup = lane_prev(mu);   // mu_{k-1}
         const double tl = du - lo, tu = hi - du;
+        const double itl = 1.0 / tl, itu = 1.0 / tu;   // IEEE: a zero slack gives infinity
         const double wdu = s.WUU * du + wxu * dxk;
         const double ru = wdu - mu * s.B - nl + nu;
-        const double Rt = s.WUU + nl / tl + nu / tu;
+        const double Rt = s.WUU + nl * itl + nu * itu;
         const double rt = ru + nl - nu;
         const double wdx = wxp * dxk + wxu * du;
         const double rx = wdx + fxp - mu * s.A + mup;
@@ -323,7 +386,7 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
         m = Mob{lane_next(m.m00, 1.0, N), lane_next(m.m01, 0.0, N), lane_next(m.m10, 0.0, N),
                 lane_next(m.m11, 1.0, N)};
         m = scan_mob_suffix(mob_norm(m), span);
-        const double Pn = (m.m00 * PN + m.m01) / (m.m10 * PN + m.m11);   // P_{k+1}
+        const double Pn = (m.m00 * PN + m.m01) * rcp_nr(m.m10 * PN + m.m11);   // P_{k+1}
         const double Huu = Rt + s.B * s.B * Pn;
         if (__ballot(act && !(Huu > 0.0))) {
             iters = it;
@@ -354,15 +417,16 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
         double fa = act ? g : 1.0, fb = act ? s.B * kf : 0.0;
         scan_affine_prefix(fa, fb, span);
         // (lane shifts run on the whole wavefront, outside any lane condition)
-        const double dxa = lane_prev(fb, 0.0);    // affine dx_k
+        const double dxa = lane_prev(fb);    // affine dx_k
         const double dua = (lane >= 1 ? K * dxa : 0.0) + kf;
-        const double dnla = -nl - nl * dua / tl, dnua = -nu + nu * dua / tu;
+        const double dnla = -nl - nl * dua * itl, dnua = -nu + nu * dua * itu;
         double apl = 1.0, adl = 1.0;
         if (act) {
-            if (dua < 0.0) apl = fmin(apl, -tl / dua);
-            if (dua > 0.0) apl = fmin(apl, tu / dua);
-            if (dnla < 0.0) adl = fmin(adl, -nl / dnla);
-            if (dnua < 0.0) adl = fmin(adl, -nu / dnua);
+            const double q = rcp_nr(dua);
+            if (dua < 0.0) apl = fmin(apl, -tl * q);
+            if (dua > 0.0) apl = fmin(apl, tu * q);
+            if (dnla < 0.0) adl = fmin(adl, -nl * rcp_nr(dnla));
+            if (dnua < 0.0) adl = fmin(adl, -nu * rcp_nr(dnua));
         }
         const double apr = wave_min(apl), adr = wave_min(adl);
         const double maff =
@@ -373,7 +437,7 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
         // corrector: the centred, second-order-corrected complementarity
         // targets in the Riccati vector, then the forward steps
         const double taul = smu - dua * dnla, tauu = smu + dua * dnua;
-        const double rt2 = ru + nl - taul / tl - nu + tauu / tu;
+        const double rt2 = ru + nl - taul * itl - nu + tauu * itu;
         double ca = hasx ? g : 1.0, cb = hasx ? fma(K, rt2, rx) : 0.0;
         ca = lane_next(ca, 1.0, N);
         cb = lane_next(cb, 0.0, N);
@@ -383,17 +447,18 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
         double ga = act ? g : 1.0, gb = act ? s.B * kf2 : 0.0;
         scan_affine_prefix(ga, gb, span);
         const double ddx = gb;                  // dx_{k+1} step
-        const double ddxk = lane_prev(gb, 0.0);
+        const double ddxk = lane_prev(gb);
         const double ddu = (lane >= 1 ? K * ddxk : 0.0) + kf2;
         const double dmu = -(Pn * ddx + e2);
-        const double dnl = (-tl * nl + taul - nl * ddu) / tl;
-        const double dnu = (-tu * nu + tauu + nu * ddu) / tu;
+        const double dnl = fma(taul - nl * ddu, itl, -nl);
+        const double dnu = fma(tauu + nu * ddu, itu, -nu);
         double apl2 = 1.0, adl2 = 1.0;
         if (act) {
-            if (ddu < 0.0) apl2 = fmin(apl2, -tl / ddu);
-            if (ddu > 0.0) apl2 = fmin(apl2, tu / ddu);
-            if (dnl < 0.0) adl2 = fmin(adl2, -nl / dnl);
-            if (dnu < 0.0) adl2 = fmin(adl2, -nu / dnu);
+            const double q = rcp_nr(ddu);
+            if (ddu < 0.0) apl2 = fmin(apl2, -tl * q);
+            if (ddu > 0.0) apl2 = fmin(apl2, tu * q);
+            if (dnl < 0.0) adl2 = fmin(adl2, -nl * rcp_nr(dnl));
+            if (dnu < 0.0) adl2 = fmin(adl2, -nu * rcp_nr(dnu));
         }
         const double ap = fmin(1.0, 0.995 * wave_min(apl2));
         const double ad = fmin(1.0, 0.995 * wave_min(adl2));
@@ -548,8 +613,8 @@ __device__ __forceinline__ bool ms_sqp_lanes(const DevParams& p, int N, int span
         // block k = {x_k, u_k} on lane k (block 0 = {u_0}); block N = {x_N}
         // on lane N - 1; W_{x_k} comes from lane k - 1 and goes back to it
         double wa = lane_prev(v.WXX, 1.0);
-        const double sxk = lane_prev(sx, 0.0);
-        const double dfx = lane_prev(fxn - v.FX, 0.0);   // change of df/dx_k
+        const double sxk = lane_prev(sx);
+        const double dfx = lane_prev(fxn - v.FX);   // change of df/dx_k
         int applied = 0;
         if (lane == 0) {
             applied = ms_bfgs1(v.WUU, su, -lam * (Bn - v.B));
