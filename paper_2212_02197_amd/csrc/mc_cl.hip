@@ -39,7 +39,7 @@ thread_local std::string g_hip_error;
 __global__ void plan_kernel(DevParams p, int64_t S, int32_t* kind, int32_t* N, int32_t* L) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= S) return;
-    const Setup s = sample_setup(p, t);
+    const Setup s = sample_setup(t);
     kind[t] = s.kind;
     N[t] = s.N;
     L[t] = s.L;

@@ -366,7 +366,18 @@ struct Setup {
 // Set-up of the sample in column `col`: its global id (caller-given or
 // id_offset + col), noise id, kind, horizon and length (caller-given or
 // drawn), scenario, kinetics and initial state.
-__device__ __noinline__ Setup sample_setup(const DevParams& p, int64_t col) {
+//
+// Every kernel of the library takes its DevParams as its first argument;
+// the set-up reads them in place from the kernel's argument segment
+// (constant memory, scalar loads), so no copy of the parameters is made in
+// per-lane scratch memory and the kernels keep reading theirs from the
+// argument segment too.
+typedef const __attribute__((address_space(4))) char* KernargPtr;
+__device__ __forceinline__ KernargPtr kernel_args() {
+    return (KernargPtr)__builtin_amdgcn_kernarg_segment_ptr();
+}
+__device__ __noinline__ Setup sample_setup_k(KernargPtr args, int64_t col) {
+    const DevParams& p = *(const DevParams*)args;
     Setup s;
     const int64_t sid = p.ids ? p.ids[col] : p.id_offset + col;
     const int64_t nid = p.noise_mod > 0 ? sid % p.noise_mod : sid;
@@ -423,6 +434,9 @@ __device__ __noinline__ Setup sample_setup(const DevParams& p, int64_t col) {
         s.xhat0 = T * p.V;
     }
     return s;
+}
+__device__ __forceinline__ Setup sample_setup(int64_t col) {
+    return sample_setup_k(kernel_args(), col);
 }
 
 // ---------------------------------------------------- single shooting ---

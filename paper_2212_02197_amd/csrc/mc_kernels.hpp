@@ -703,7 +703,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVE
         const int64_t idx = (int64_t)grp * wk.spw + lane;
         const bool has = lane < wk.spw && idx < wk.n_pos;
         const int64_t pos = has ? wk.pos[idx] : 0;
-        Setup su = sample_setup(p, pos);
+        Setup su = sample_setup(pos);
         const int N = has ? su.N : 1;
         const int L = has ? su.L : -1;
         int cnt[C_NCNT];
@@ -844,7 +844,7 @@ __global__ __launch_bounds__(64) void pi_kernel(DevParams p, const int64_t* pos_
     }
     if (t >= t1) return;
     const int64_t pos = pos_list[t];
-    const Setup su = sample_setup(p, pos);
+    const Setup su = sample_setup(pos);
     const double sqrtR = sqrt(p.Rmeas);
     const double h = p.Ts / (double)p.Ns;
     const double sqh = sqrt(h);
@@ -934,7 +934,7 @@ __global__ __launch_bounds__(64) void pi_reverse_kernel(DevParams p, const int64
     const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (t >= npi) return;
     const int64_t pos = pos_list[t];
-    const Setup su = sample_setup(p, pos);
+    const Setup su = sample_setup(pos);
     const double sqrtR = sqrt(p.Rmeas);
     const double h = p.Ts / (double)p.Ns;
     const double sqh = sqrt(h);

@@ -680,7 +680,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_MS_WAVES_
         grp = uni(__shfl(grp, 0, 64));
         if (grp >= g_hi) break;
         const int64_t pos = wk.pos[grp];
-        const Setup su = sample_setup(p, pos);
+        const Setup su = sample_setup(pos);
         const int N = uni(su.N);
         const int L = uni(su.L);
         int span = 1;
