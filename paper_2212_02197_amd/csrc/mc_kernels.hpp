@@ -15,8 +15,17 @@
 #include "mc_coop.hpp"
 #include "mc_dev.hpp"
 
+// Wavefronts per SIMD the NMPC kernel is built for.  At NMAX = 64 the
+// kernel needs its 512 registers per lane whatever is asked (one wave per
+// SIMD), but asking for two makes the register allocator spill about 100
+// registers instead of about 600 (c1: 5.71 s against 6.09 s per campaign).
+// At NMAX 16 and 32 the request does give two waves per SIMD, with more
+// spills, and that is slower (c4: 11.98 s against 10.09 s): one.
+#ifndef MC_NMPC_WAVES_PER_EU_64
+#define MC_NMPC_WAVES_PER_EU_64 2
+#endif
 #ifndef MC_NMPC_WAVES_PER_EU
-#define MC_NMPC_WAVES_PER_EU 1   // wavefronts per SIMD the NMPC kernel is built for
+#define MC_NMPC_WAVES_PER_EU 1
 #endif
 
 namespace mccl {
@@ -682,7 +691,7 @@ __device__ __forceinline__ bool sqp_group(const DevParams& p, bool live, int N, 
 }
 
 template <int NMAX, int GMODE, int NX>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_NMPC_WAVES_PER_EU))) void nmpc_kernel(DevParams p, NmpcWork wk, Outs out) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NMAX == 64 ? MC_NMPC_WAVES_PER_EU_64 : MC_NMPC_WAVES_PER_EU))) void nmpc_kernel(DevParams p, NmpcWork wk, Outs out) {
     // staged W (or H) of one sample, then two broadcast vectors (lds_vec)
     __shared__ __attribute__((aligned(16))) double Wl[NMAX * NMAX + 2 * NMAX];
     const int lane = threadIdx.x;
