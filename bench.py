@@ -55,13 +55,17 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_sha256():
-    """Hash of the kernel sources (csrc/*.hpp, csrc/*.hip sorted by name)."""
+def kernel_source_sha256(multiple_shooting=False):
+    """Hash of the kernel sources (csrc/*.hpp, csrc/*.hip sorted by name).
+    The single-shooting and PI kernels do not depend on mc_ms.hpp (the
+    multiple-shooting kernel), so their hash leaves it out unless asked."""
     import glob
     import hashlib
     d = os.path.join(ROOT, "paper_2212_02197_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(d, "*.hpp")) + glob.glob(os.path.join(d, "*.hip"))):
+        if not multiple_shooting and os.path.basename(f) == "mc_ms.hpp":
+            continue
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
