@@ -91,16 +91,20 @@ hipError_t launch_nmpc(const DevParams& dp, const NmpcWork& wk, const Outs& o, i
     return hipGetLastError();
 }
 
+// Multiple shooting: the horizon class NMAX is the segment width (samples
+// per wavefront 64 / NMAX).
+template <int G>
 hipError_t launch_ms(const DevParams& dp, const NmpcWork& wk, const Outs& o, int slots,
                      hipStream_t st) {
     MsWork mw{wk.pos, wk.n_pos, wk.n_groups, wk.queue, wk.qhi};
-    hipLaunchKernelGGL(nmpc_ms_kernel, dim3(slots), dim3(64), 0, st, dp, mw, o);
+    hipLaunchKernelGGL(nmpc_ms_kernel<G>, dim3(slots), dim3(64), 0, st, dp, mw, o);
     return hipGetLastError();
 }
 
+template <int G>
 int ms_blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, nmpc_ms_kernel, 64, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, nmpc_ms_kernel<G>, 64, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
@@ -117,7 +121,8 @@ int max_blocks_per_cu() {
 // Kernel variants: horizon class NMAX x gradient mode x model states; the
 // three-state model runs with the adjoint gradient only (validated).
 int blocks_per_cu(int nmax, int gmode, int nx, int nlp_form = 0) {
-    if (nlp_form == 1) return ms_blocks_per_cu();
+    if (nlp_form == 1)
+        return nmax == 16 ? ms_blocks_per_cu<16>() : nmax == 32 ? ms_blocks_per_cu<32>() : ms_blocks_per_cu<64>();
     if (nx == 3) {
         if (nmax == 16) return max_blocks_per_cu<16, 1, 3>();
         if (nmax == 32) return max_blocks_per_cu<32, 1, 3>();
@@ -135,7 +140,9 @@ int blocks_per_cu(int nmax, int gmode, int nx, int nlp_form = 0) {
 
 hipError_t dispatch_nmpc(int nmax, int gmode, int nx, const DevParams& dp, const NmpcWork& wk,
                          const Outs& o, int slots, hipStream_t st) {
-    if (dp.nlp_form == 1) return launch_ms(dp, wk, o, slots, st);
+    if (dp.nlp_form == 1)
+        return nmax == 16 ? launch_ms<16>(dp, wk, o, slots, st)
+               : nmax == 32 ? launch_ms<32>(dp, wk, o, slots, st) : launch_ms<64>(dp, wk, o, slots, st);
     if (nx == 3) {
         if (nmax == 16) return launch_nmpc<16, 1, 3>(dp, wk, o, slots, st);
         if (nmax == 32) return launch_nmpc<32, 1, 3>(dp, wk, o, slots, st);
@@ -413,10 +420,13 @@ static int validate(const mc_cl_params* p) {
 // class's wave-slot workspaces when the shape needs more of them.
 static int plan_class(mc_cl_ctx* c, NmpcClass& nc, int spw) {
     const bool ms = c->prm.nlp_form == 1;
-    if (ms) spw = 1;   // one sample per wavefront, a stage per lane
+    // multiple shooting: the queue hands out single samples, each taken by
+    // an NMAX-lane segment (a stage per lane), 64 / NMAX segments per wavefront
+    if (ms) spw = 1;
     nc.spw = spw;
     nc.groups = (int)((nc.count + spw - 1) / spw);
-    nc.slots = std::min(nc.groups, nc.slots_full);
+    const int per_wave = ms ? 64 / nc.nmax : 1;
+    nc.slots = std::min((nc.groups + per_wave - 1) / per_wave, nc.slots_full);
     // multiple shooting keeps every stage quantity in registers
     nc.tile_stride = ms ? 0 : (int64_t)V_COUNT * nc.nmax * 64;
     nc.xs_stride = ms ? 0 : (int64_t)(c->prm.model_nx == 3 ? rec_width<3>() : rec_width<1>()) * nc.nmax * 64;

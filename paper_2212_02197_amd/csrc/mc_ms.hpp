@@ -222,6 +222,125 @@ __device__ __forceinline__ Mob scan_mob_suffix(Mob m, int span) {
     return m;
 }
 
+// ------------------------------------------------------------ segments ---
+// A wavefront holds 64 / G samples, sample j on the segment of lanes
+// [jG, (j + 1)G), stage k of a sample on lane jG + k (G = 16, 32 or 64:
+// horizons up to 16 take a 16-lane row each, up to 32 two rows).  Every
+// lane shift, broadcast, reduction and scan below stays inside a segment,
+// so a segment whose lanes are inactive (its sample done, or at another
+// point of its control flow) never feeds another segment.
+template <int G>
+struct Seg {
+    static_assert(G == 16 || G == 32 || G == 64, "segments of 16, 32 or 64 lanes");
+    __device__ static __forceinline__ int k() { return (int)threadIdx.x & (G - 1); }
+    __device__ static __forceinline__ int base() { return (int)threadIdx.x & (64 - G); }
+    // v of stage k - 1 (stage 0: 0, or `fill`); of stage k + 1 (stages
+    // >= n - 1: `fill`)
+    __device__ static __forceinline__ double prev(double v) {
+        if constexpr (G == 16) {
+            return dpp_z<0x111>(v);   // row_shr:1: a row is a segment
+        } else {
+            const double w = dpp_z<0x138>(v);   // wave_shr:1
+            if constexpr (G == 64) return w;
+            else return k() == 0 ? 0.0 : w;
+        }
+    }
+    __device__ static __forceinline__ double prev(double v, double fill) {
+        if constexpr (G == 16) {
+            return dpp_d<0x111, 0xf>(fill, v);
+        } else {
+            const double w = dpp_d<0x138, 0xf>(fill, v);
+            if constexpr (G == 64) return w;
+            else return k() == 0 ? fill : w;
+        }
+    }
+    __device__ static __forceinline__ double next(double v, double fill, int n) {
+        const double w = G == 16 ? dpp_z<0x101>(v) : dpp_z<0x130>(v);   // row_shl:1 / wave_shl:1
+        return k() + 1 < n ? w : fill;
+    }
+    // v of stage j of this segment (j the same on the whole segment; at
+    // G = 64 the same on the whole wavefront)
+    __device__ static __forceinline__ double bcast(double v, int j) {
+        if constexpr (G == 64) return readlane_d(v, j);
+        else return __shfl(v, base() + j, 64);
+    }
+    // sum, maximum, minimum over the segment, in every lane of it: rows by
+    // DPP, the two rows of a 32-lane segment by the gfx950 row-pair swap
+    template <typename Op>
+    __device__ static __forceinline__ double fold(double v, Op op) {
+        v = op(v, dpp_z<0xB1>(v));    // quad_perm [1,0,3,2]
+        v = op(v, dpp_z<0x4E>(v));    // quad_perm [2,3,0,1]
+        v = op(v, dpp_z<0x124>(v));   // row_ror:4
+        v = op(v, dpp_z<0x128>(v));   // row_ror:8
+        if constexpr (G == 32) {
+            const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+            const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+            v = op(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
+        }
+        return v;
+    }
+    __device__ static __forceinline__ double sum(double v) {
+        if constexpr (G == 64) return wave_sum(v);
+        else return fold(v, [](double a, double b) { return a + b; });
+    }
+    __device__ static __forceinline__ double max(double v) {
+        if constexpr (G == 64) return wave_max(v);
+        else return fold(v, [](double a, double b) { return fmax(a, b); });
+    }
+    __device__ static __forceinline__ double min(double v) {
+        if constexpr (G == 64) return wave_min(v);
+        else return fold(v, [](double a, double b) { return fmin(a, b); });
+    }
+    // some lane of the segment has c
+    __device__ static __forceinline__ bool any(bool c) {
+        const uint64_t m = __ballot(c);
+        if constexpr (G == 64) return m != 0;
+        else return ((m >> base()) & ((1ull << G) - 1)) != 0;
+    }
+    // the bit mask of lanes k < n of the segment with c (bit k)
+    __device__ static __forceinline__ uint64_t mask(bool c) {
+        const uint64_t m = __ballot(c);
+        if constexpr (G == 64) return m;
+        else return (m >> base()) & ((1ull << G) - 1);
+    }
+    // inclusive prefix / suffix scans of affine maps inside the segment
+    __device__ static __forceinline__ Aff scan_prefix_aff(Aff f, int span) {
+        const Aff id{1.0, 0.0};
+        if constexpr (G == 64) return scan_prefix(f, id, span, aff_after);
+        const int r = threadIdx.x & 15;
+        f = aff_after(f, DppOps<Aff>::row<0x111>(f, r >= 1));
+        f = aff_after(f, DppOps<Aff>::row<0x112>(f, r >= 2));
+        f = aff_after(f, DppOps<Aff>::row<0x114>(f, r >= 4));
+        f = aff_after(f, DppOps<Aff>::row<0x118>(f, r >= 8));
+        if constexpr (G == 32) f = aff_after(f, DppOps<Aff>::mov<0x142, 0xa>(id, f));   // row_bcast:15
+        return f;
+    }
+    template <class T, class After>
+    __device__ static __forceinline__ T suffix_rows(T f, T id, After after, bool norm_pairs) {
+        const int r = threadIdx.x & 15;
+        f = after(f, DppOps<T>::template row<0x101>(f, r <= 14));
+        f = after(f, DppOps<T>::template row<0x102>(f, r <= 13));
+        f = after(f, DppOps<T>::template row<0x104>(f, r <= 11));
+        f = after(f, DppOps<T>::template row<0x108>(f, r <= 7));
+        if constexpr (G == 32) {
+            // row 0 composes with row 1's total (lane 16), row 2 with row 3's (lane 48)
+            const int row = threadIdx.x >> 4;
+            const T t1 = DppOps<T>::readlane(f, 16), t3 = DppOps<T>::readlane(f, 48);
+            f = after(f, row == 0 ? t1 : row == 2 ? t3 : id);
+        }
+        (void)norm_pairs;
+        return f;
+    }
+    __device__ static __forceinline__ Aff scan_suffix_aff(Aff f, int span) {
+        if constexpr (G == 64) return scan_suffix(f, Aff{1.0, 0.0}, span, aff_after);
+        else return suffix_rows(f, Aff{1.0, 0.0}, aff_after, false);
+    }
+    __device__ static __forceinline__ Mob scan_suffix_mob(Mob m, int span) {
+        if constexpr (G == 64) return scan_mob_suffix(m, span);
+        else return suffix_rows(m, Mob{1.0, 0.0, 0.0, 1.0}, mob_after, true);
+    }
+};
+
 // One sampling interval of the one-state model, RK4 with Nc steps: returns
 // F(x, u); with kDeriv also A = dF/dx, B = dF/du (u in mL/min) by the
 // tangent-linear RK4, the exact derivatives of the discrete map.
@@ -328,17 +447,19 @@ struct MsQpOut {
     double du, dx, mu, nl, nu;
 };
 
+template <int G>
 __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, MsStage s,
                                         MsQpOut& o, int& iters) {
-    const int lane = threadIdx.x;
+    using S = Seg<G>;
+    const int lane = S::k();   // the stage of this lane
     const bool act = lane < N;
     const bool hasx = act && lane >= 1;   // the stage has a state x_k in the NLP
     const double lo = p.umin - s.U, hi = p.umax - s.U;
     const double wxu = lane >= 1 ? s.WXU : 0.0;
-    const double wxp = lane_prev(s.WXX);    // W_{x_k}
-    const double fxp = lane_prev(s.FX);     // df/dx_k
-    const double PN = readlane_d(s.WXX, N - 1);  // W_{x_N}
-    const double fxN = readlane_d(s.FX, N - 1);
+    const double wxp = S::prev(s.WXX);    // W_{x_k}
+    const double fxp = S::prev(s.FX);     // df/dx_k
+    const double PN = S::bcast(s.WXX, N - 1);  // W_{x_N}
+    const double fxN = S::bcast(s.FX, N - 1);
     double du, nl = 1.0, nu = 1.0, mu = 0.0, dx;
     {
         const double dl = 1e-2 * (hi - lo);
@@ -346,16 +467,20 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
         if (du < lo + dl) du = lo + dl;
         if (du > hi - dl) du = hi - dl;
         double a = act ? s.A : 1.0, b = act ? fma(s.B, du, s.C) : 0.0;
-        scan_affine_prefix(a, b, span);
+        {
+            const Aff r = S::scan_prefix_aff(Aff{a, b}, span);
+            a = r.a;
+            b = r.b;
+        }
         dx = b;   // dx_{k+1}; dx_0 = 0
     }
-    const double gsc = wave_max(act ? fabs(s.FX) : 0.0);
+    const double gsc = S::max(act ? fabs(s.FX) : 0.0);
     const double inv2N = 1.0 / (2.0 * N);
     #pragma unroll 1
     for (int it = 0;; ++it) {
         // residuals of the current point
-        const double dxk = lane_prev(dx);   // dx_k (dx_0 = 0)
-        const double mup = lane_prev(mu);   // mu_{k-1}
+        const double dxk = S::prev(dx);   // dx_k (dx_0 = 0)
+        const double mup = S::prev(mu);   // mu_{k-1}
         const double tl = du - lo, tu = hi - du;
         const double itl = 1.0 / tl, itu = 1.0 / tu;   // IEEE: a zero slack gives infinity
         const double wdu = s.WUU * du + wxu * dxk;
@@ -364,16 +489,16 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
         const double rt = ru + nl - nu;
         const double wdx = wxp * dxk + wxu * du;
         const double rx = wdx + fxp - mu * s.A + mup;
-        const double dxN = readlane_d(dx, N - 1), muN = readlane_d(mu, N - 1);
+        const double dxN = S::bcast(dx, N - 1), muN = S::bcast(mu, N - 1);
         const double rxN = PN * dxN + fxN + muN;
         double rl = act ? fabs(ru) : 0.0, wl = act ? fabs(wdu) : 0.0;
         if (hasx) {
             rl = fmax(rl, fabs(rx));
             wl = fmax(wl, fabs(wdx));
         }
-        const double rmax = fmax(fabs(rxN), wave_max(rl));
-        const double wd = fmax(fabs(PN * dxN), wave_max(wl));
-        const double comp = wave_sum(act ? tl * nl + tu * nu : 0.0);
+        const double rmax = fmax(fabs(rxN), S::max(rl));
+        const double wd = fmax(fabs(PN * dxN), S::max(wl));
+        const double comp = S::sum(act ? tl * nl + tu * nu : 0.0);
         // Riccati factor: lane k composes the maps of stages k+1..N-1
         // (divided by R~_k: a slack that has reached 0 in floating point makes
         // R~_k infinite, and the map tends to P -> A_k^2 P + W_{x_k})
@@ -383,12 +508,12 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
             m = Mob{fma(s.A, s.A, (wxp * s.B * s.B - 2.0 * wxu * s.A * s.B) * rR), fma(-wxu * wxu, rR, wxp),
                     s.B * s.B * rR, 1.0};
         }
-        m = Mob{lane_next(m.m00, 1.0, N), lane_next(m.m01, 0.0, N), lane_next(m.m10, 0.0, N),
-                lane_next(m.m11, 1.0, N)};
-        m = scan_mob_suffix(mob_norm(m), span);
+        m = Mob{S::next(m.m00, 1.0, N), S::next(m.m01, 0.0, N), S::next(m.m10, 0.0, N),
+                S::next(m.m11, 1.0, N)};
+        m = S::scan_suffix_mob(mob_norm(m), span);
         const double Pn = (m.m00 * PN + m.m01) * rcp_nr(m.m10 * PN + m.m11);   // P_{k+1}
         const double Huu = Rt + s.B * s.B * Pn;
-        if (__ballot(act && !(Huu > 0.0))) {
+        if (S::any(act && !(Huu > 0.0))) {
             iters = it;
             return -1;
         }
@@ -397,9 +522,13 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
         const double g = lane >= 1 ? fma(s.B, K, s.A) : 0.0;   // closed-loop gain of stage k
         // predictor's Riccati vector: lane k composes p-maps of stages k+1..N-1
         double va = hasx ? g : 1.0, vb = hasx ? fma(K, rt, rx) : 0.0;
-        va = lane_next(va, 1.0, N);
-        vb = lane_next(vb, 0.0, N);
-        scan_affine_suffix(va, vb, span);
+        va = S::next(va, 1.0, N);
+        vb = S::next(vb, 0.0, N);
+        {
+            const Aff r = S::scan_suffix_aff(Aff{va, vb}, span);
+            va = r.a;
+            vb = r.b;
+        }
         const double e = fma(va, rxN, vb);      // p_{k+1}
         const double kf = -(rt + s.B * e) * hinv;
         const double muc = comp * inv2N;
@@ -415,9 +544,13 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
         }
         // forward predictor: affine step and its lengths
         double fa = act ? g : 1.0, fb = act ? s.B * kf : 0.0;
-        scan_affine_prefix(fa, fb, span);
+        {
+            const Aff r = S::scan_prefix_aff(Aff{fa, fb}, span);
+            fa = r.a;
+            fb = r.b;
+        }
         // (lane shifts run on the whole wavefront, outside any lane condition)
-        const double dxa = lane_prev(fb);    // affine dx_k
+        const double dxa = S::prev(fb);    // affine dx_k
         const double dua = (lane >= 1 ? K * dxa : 0.0) + kf;
         const double dnla = -nl - nl * dua * itl, dnua = -nu + nu * dua * itu;
         double apl = 1.0, adl = 1.0;
@@ -428,9 +561,9 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
             if (dnla < 0.0) adl = fmin(adl, -nl * rcp_nr(dnla));
             if (dnua < 0.0) adl = fmin(adl, -nu * rcp_nr(dnua));
         }
-        const double apr = wave_min(apl), adr = wave_min(adl);
+        const double apr = S::min(apl), adr = S::min(adl);
         const double maff =
-            wave_sum(act ? (tl + apr * dua) * (nl + adr * dnla) + (tu - apr * dua) * (nu + adr * dnua)
+            S::sum(act ? (tl + apr * dua) * (nl + adr * dnla) + (tu - apr * dua) * (nu + adr * dnua)
                          : 0.0) * inv2N;
         const double ratio = muc > 0.0 ? maff / muc : 0.0;
         const double smu = ratio * ratio * ratio * muc;   // sigma mu
@@ -439,15 +572,23 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
         const double taul = smu - dua * dnla, tauu = smu + dua * dnua;
         const double rt2 = ru + nl - taul * itl - nu + tauu * itu;
         double ca = hasx ? g : 1.0, cb = hasx ? fma(K, rt2, rx) : 0.0;
-        ca = lane_next(ca, 1.0, N);
-        cb = lane_next(cb, 0.0, N);
-        scan_affine_suffix(ca, cb, span);
+        ca = S::next(ca, 1.0, N);
+        cb = S::next(cb, 0.0, N);
+        {
+            const Aff r = S::scan_suffix_aff(Aff{ca, cb}, span);
+            ca = r.a;
+            cb = r.b;
+        }
         const double e2 = fma(ca, rxN, cb);     // p_{k+1}
         const double kf2 = -(rt2 + s.B * e2) * hinv;
         double ga = act ? g : 1.0, gb = act ? s.B * kf2 : 0.0;
-        scan_affine_prefix(ga, gb, span);
+        {
+            const Aff r = S::scan_prefix_aff(Aff{ga, gb}, span);
+            ga = r.a;
+            gb = r.b;
+        }
         const double ddx = gb;                  // dx_{k+1} step
-        const double ddxk = lane_prev(gb);
+        const double ddxk = S::prev(gb);
         const double ddu = (lane >= 1 ? K * ddxk : 0.0) + kf2;
         const double dmu = -(Pn * ddx + e2);
         const double dnl = fma(taul - nl * ddu, itl, -nl);
@@ -460,8 +601,8 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
             if (dnl < 0.0) adl2 = fmin(adl2, -nl * rcp_nr(dnl));
             if (dnu < 0.0) adl2 = fmin(adl2, -nu * rcp_nr(dnu));
         }
-        const double ap = fmin(1.0, 0.995 * wave_min(apl2));
-        const double ad = fmin(1.0, 0.995 * wave_min(adl2));
+        const double ap = fmin(1.0, 0.995 * S::min(apl2));
+        const double ad = fmin(1.0, 0.995 * S::min(adl2));
         if (act) {
             du = du + ap * ddu;
             dx = dx + ap * ddx;
@@ -479,10 +620,12 @@ struct MsNlp {
 
 // The SQP of one OCP from x-hat (x0) with the warm-started inputs in U;
 // returns true if the KKT test passed (else the last iterate stands).
+template <int G>
 __device__ __forceinline__ bool ms_sqp_lanes(const DevParams& p, int N, int span, double x0,
                                              int i0, int istep, double sign, double& Uio,
                                              int (&cnt)[C_NCNT]) {
-    const int lane = threadIdx.x;
+    using S = Seg<G>;
+    const int lane = S::k();   // the stage of this lane
     const bool act = lane < N;
     const double smax = 100.0;
     const double cst = 2.0 * p.Qz * p.Ts / p.V;
@@ -498,21 +641,21 @@ __device__ __forceinline__ bool ms_sqp_lanes(const DevParams& p, int N, int span
         #pragma unroll 1
         for (int k = 0; k < N; ++k) {
             double dA, dB;
-            xk = ms_interval<false>(p, xk, readlane_d(v.U, k), dA, dB);
+            xk = ms_interval<false>(p, xk, S::bcast(v.U, k), dA, dB);
             if (lane == k) X = xk;
         }
         v.X = X;
     }
     // interval tangents at (x_k, u_k), all stages at once
     {
-        const double F = ms_interval<true>(p, lane_prev(v.X, x0), v.U, v.A, v.B);
+        const double F = ms_interval<true>(p, S::prev(v.X, x0), v.U, v.A, v.B);
         v.C = F - v.X;
     }
     double f;
     {
         const double ez = v.X / p.V - zb;
         v.FX = cst * ez;
-        f = wave_sum(act ? qt * ez * ez : 0.0);
+        f = S::sum(act ? qt * ez * ez : 0.0);
     }
     if (!act) v.A = v.B = v.C = v.FX = 0.0;
     v.WXX = 1.0;
@@ -525,12 +668,12 @@ __device__ __forceinline__ bool ms_sqp_lanes(const DevParams& p, int N, int span
     #pragma unroll 1
     for (int l = 0;; ++l) {
         // eq. (convergence): |grad L / s_d|_inf <= eps and |c|_inf <= eps
-        const double s1 = wave_sum(act ? fabs(v.LAM) + fabs(v.PIL) + fabs(v.PIU) : 0.0);
+        const double s1 = S::sum(act ? fabs(v.LAM) + fabs(v.PIL) + fabs(v.PIU) : 0.0);
         const double gu = -v.LAM * v.B - v.PIL + v.PIU;
-        const double gx = v.FX + v.LAM - lane_next(v.LAM * v.A, 0.0, N);
-        const bool bad = __ballot(act && (!(gu == gu) || !(gx == gx) || !(v.C == v.C))) != 0;
-        const double gmax = wave_max(act ? fmax(fabs(gu), fabs(gx)) : 0.0);
-        const double cmax = wave_max(act ? fabs(v.C) : 0.0);
+        const double gx = v.FX + v.LAM - S::next(v.LAM * v.A, 0.0, N);
+        const bool bad = S::any(act && (!(gu == gu) || !(gx == gx) || !(v.C == v.C)));
+        const double gmax = S::max(act ? fmax(fabs(gu), fabs(gx)) : 0.0);
+        const double cmax = S::max(act ? fabs(v.C) : 0.0);
         const double sd = fmax(smax, s1 / (3.0 * N)) / smax;
         if (!bad && gmax / sd <= p.sqp_eps && cmax <= p.sqp_eps) {
             Uio = v.U;
@@ -543,9 +686,9 @@ __device__ __forceinline__ bool ms_sqp_lanes(const DevParams& p, int N, int span
         // QP; an indefinite block (or H_uu <= 0 in the recursion) resets W
         bool reset;
         {
-            const double wxp = lane_prev(v.WXX, 1.0);
+            const double wxp = S::prev(v.WXX, 1.0);
             const bool pdl = v.WUU > 0.0 && v.WXX > 0.0 && (lane == 0 || wxp * v.WUU - v.WXU * v.WXU > 0.0);
-            reset = __ballot(act && !pdl) != 0;
+            reset = S::any(act && !pdl);
         }
         MsQpOut q{0.0, 0.0, 0.0, 0.0, 0.0};
         int st;
@@ -558,7 +701,7 @@ __device__ __forceinline__ bool ms_sqp_lanes(const DevParams& p, int N, int span
                 v.WUU = 1.0;
             }
             int it = 0;
-            st = ms_qp_lanes(p, N, span, MsStage{v.U, v.A, v.B, v.C, v.FX, v.WXX, v.WXU, v.WUU}, q, it);
+            st = ms_qp_lanes<G>(p, N, span, MsStage{v.U, v.A, v.B, v.C, v.FX, v.WXX, v.WXU, v.WUU}, q, it);
             cnt[C_IPM] += it;
             if (st != -1 || reset) break;
             reset = true;
@@ -572,8 +715,8 @@ __device__ __forceinline__ bool ms_sqp_lanes(const DevParams& p, int N, int span
         }
         first = false;
         const double ac = fabs(v.C);
-        const double T0 = f + wave_sum(act ? v.SIG * ac : 0.0);
-        const double D = wave_sum(act ? v.FX * q.dx - v.SIG * ac : 0.0);
+        const double T0 = f + S::sum(act ? v.SIG * ac : 0.0);
+        const double D = S::sum(act ? v.FX * q.dx - v.SIG * ac : 0.0);
         double alpha = 1.0;
         #pragma unroll 1
         for (int bt = 0;; ++bt) {
@@ -581,9 +724,9 @@ __device__ __forceinline__ bool ms_sqp_lanes(const DevParams& p, int N, int span
             const double xn = v.X + alpha * q.dx;
             const double u = v.U + alpha * q.du;
             double dA, dB;
-            const double F = ms_interval<false>(p, lane_prev(xn, x0), u, dA, dB);
+            const double F = ms_interval<false>(p, S::prev(xn, x0), u, dA, dB);
             const double ez = xn / p.V - zb;
-            const double Tt = wave_sum(act ? v.SIG * fabs(F - xn) + qt * ez * ez : 0.0);
+            const double Tt = S::sum(act ? v.SIG * fabs(F - xn) + qt * ez * ez : 0.0);
             cnt[C_LS]++;
             // a predicted decrease below the merit's resolution cannot be
             // tested in floating point: the full step is taken
@@ -602,19 +745,19 @@ __device__ __forceinline__ bool ms_sqp_lanes(const DevParams& p, int N, int span
         const double sx = alpha * q.dx;           // step of x_{k+1}
         const double xk1 = v.X + sx;
         double An, Bn;
-        const double F = ms_interval<true>(p, lane_prev(xk1, x0), un, An, Bn);
+        const double F = ms_interval<true>(p, S::prev(xk1, x0), un, An, Bn);
         const double lam = v.LAM + alpha * (q.mu - v.LAM);
         v.LAM = lam;
         v.PIL = v.PIL + alpha * (q.nl - v.PIL);
         v.PIU = v.PIU + alpha * (q.nu - v.PIU);
         const double ez = xk1 / p.V - zb;
         const double fxn = cst * ez;
-        f = wave_sum(act ? qt * ez * ez : 0.0);
+        f = S::sum(act ? qt * ez * ez : 0.0);
         // block k = {x_k, u_k} on lane k (block 0 = {u_0}); block N = {x_N}
         // on lane N - 1; W_{x_k} comes from lane k - 1 and goes back to it
-        double wa = lane_prev(v.WXX, 1.0);
-        const double sxk = lane_prev(sx);
-        const double dfx = lane_prev(fxn - v.FX);   // change of df/dx_k
+        double wa = S::prev(v.WXX, 1.0);
+        const double sxk = S::prev(sx);
+        const double dfx = S::prev(fxn - v.FX);   // change of df/dx_k
         int applied = 0;
         if (lane == 0) {
             applied = ms_bfgs1(v.WUU, su, -lam * (Bn - v.B));
@@ -623,9 +766,9 @@ __device__ __forceinline__ bool ms_sqp_lanes(const DevParams& p, int N, int span
         }
         double wN = v.WXX;
         if (lane == N - 1) applied |= ms_bfgs1(wN, sx, fxn - v.FX);
-        const double wnext = lane_next(wa, 0.0, N);
+        const double wnext = S::next(wa, 0.0, N);
         if (act) v.WXX = lane == N - 1 ? wN : wnext;
-        if (__ballot(act && applied) == 0) cnt[C_SKIP]++;
+        if (!S::any(act && applied)) cnt[C_SKIP]++;
         if (act) {
             v.U = un;
             v.X = xk1;
@@ -660,82 +803,118 @@ __device__ __forceinline__ double ms_sample_flops(const DevParams& p, int N, int
 }
 
 
-// NMPC kernel of the multiple-shooting formulation: one sample per
-// wavefront (64-lane workgroup), groups of one sample taken from the work
-// queue.  The closed loop per interval is that of nmpc_kernel (cost,
+// NMPC kernel of the multiple-shooting formulation: a wavefront (64-lane
+// workgroup) holds 64 / G samples, one per G-lane segment, each segment
+// taking its next sample from the work queue as soon as its current one
+// ends.  The closed loop per interval is that of nmpc_kernel (cost,
 // measurement, CD-EKF, OCP, first input applied, Ns Euler-Maruyama
-// sub-steps); the plant and the estimator are the same on every lane, the
-// OCP runs a stage per lane.  Each OCP starts from the previous solution
-// shifted by one interval with W^[0] = I.
+// sub-steps); the plant and the estimator are the same on every lane of a
+// segment, the OCP runs a stage per lane.  The segments step their own
+// intervals together: one pass of the loop is one control interval of each
+// segment's sample.  Each OCP starts from the previous solution shifted by
+// one interval with W^[0] = I.
+template <int G>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_MS_WAVES_PER_EU))) void nmpc_ms_kernel(DevParams p, MsWork wk, Outs out) {
-    const int lane = threadIdx.x;
+    using S = Seg<G>;
+    const int kid = S::k();
     const double sqrtR = sqrt(p.Rmeas);
     const double h = p.Ts / (double)p.Ns;
     const double sqh = sqrt(h);
     const int g_hi = wk.qhi ? *wk.qhi : wk.n_groups;
+    bool busy = false, drained = false;
+    int64_t pos = 0;
+    Setup su{};
+    int N = 1, L = 0, i = 0, span = G;
+    int cnt[C_NCNT];
+    double n[3] = {0.0, 0.0, 0.0};
+    double xhat = 0.0, P = 0.0, Fprev = 0.0, phiacc = 0.0, U = 0.0;
+    uint64_t hsh = 0;
     #pragma unroll 1
     for (;;) {
-        int grp = 0;
-        if (lane == 0) grp = atomicAdd(wk.queue, 1);
-        grp = uni(__shfl(grp, 0, 64));
-        if (grp >= g_hi) break;
-        const int64_t pos = wk.pos[grp];
-        const Setup su = sample_setup(pos);
-        const int N = uni(su.N);
-        const int L = uni(su.L);
-        int span = 1;
-        while (span < N) span <<= 1;
-        int cnt[C_NCNT];
+        // a segment without a sample takes the next one (lane k = 0 of the
+        // segment draws from the queue)
+        if (!busy && !drained) {
+            int grp = 0;
+            if (kid == 0) grp = atomicAdd(wk.queue, 1);
+            grp = G == 64 ? uni(__shfl(grp, 0, 64)) : __shfl(grp, S::base(), 64);
+            if (grp >= g_hi) {
+                drained = true;
+            } else {
+                busy = true;
+                pos = wk.pos[grp];
+                su = sample_setup(pos);
+                N = G == 64 ? uni(su.N) : su.N;
+                L = G == 64 ? uni(su.L) : su.L;
+                i = 0;
+                if (G == 64) {
+                    span = 1;
+                    while (span < N) span <<= 1;
+                }
 #pragma unroll
-        for (int c = 0; c < C_NCNT; ++c) cnt[c] = 0;
-        double n[3] = {su.n0[0], su.n0[1], su.n0[2]};
-        double xhat = su.xhat0, P = p.P0, Fprev = su.ubar, phiacc = 0.0;
-        uint64_t hsh = 14695981039346656037ull;
-        double U = su.ubar * kMlMinPerLs;   // u_k of the warm start on lane k
-        #pragma unroll 1
-        for (int i = 0; i <= L; ++i) {
+                for (int c = 0; c < C_NCNT; ++c) cnt[c] = 0;
+                n[0] = su.n0[0];
+                n[1] = su.n0[1];
+                n[2] = su.n0[2];
+                xhat = su.xhat0;
+                P = p.P0;
+                Fprev = su.ubar;
+                phiacc = 0.0;
+                hsh = 14695981039346656037ull;
+                U = su.ubar * kMlMinPerLs;   // u_k of the warm start on lane k
+            }
+        }
+        if (__ballot(busy) == 0) break;
+        if (busy) {
+            // control interval i of this segment's sample
             const double z = n[2] / p.V;
             const double zb = setpoint(p, i, su.istep, su.sign);
             phiacc += (z - zb) * (z - zb);
-            if (out.tz && lane == 0) out.tz[(int64_t)i * out.S + pos] = z;
+            if (out.tz && kid == 0) out.tz[(int64_t)i * out.S + pos] = z;
+            bool done = false;
             if (!isfinite(z)) {
                 // the plant diverged (Phi is not a number): no more OCPs
                 cnt[C_NONFIN] = 1;
-                break;
+                done = true;
+            } else if (i == L) {
+                done = true;
+            } else {
+                const double y = z + p.noise_scale * sqrtR *
+                                         normal_first(p.seed, 0, (uint32_t)i, su.nid, kTagMeas);
+                ekf_predict(p, xhat, P, Fprev);
+                ekf_update(p, xhat, P, y);
+                if (!isfinite(P) || !isfinite(xhat)) cnt[C_NONFIN] = 1;
+                if (out.tx && kid == 0) out.tx[(int64_t)i * out.S + pos] = xhat;
+                const bool conv = ms_sqp_lanes<G>(p, N, span, xhat, i, su.istep, su.sign, U, cnt);
+                cnt[C_OCP]++;
+                if (!conv) cnt[C_OCP_FAIL]++;
+                const uint64_t mask = S::mask(kid < N && (U <= p.umin + 1e-6 || U >= p.umax - 1e-6));
+                hsh = fnv1a_step(hsh, (uint32_t)i, mask);
+                const double F = S::bcast(U, 0) / kMlMinPerLs;
+                U = S::next(U, U, N);   // shift: u_k <- u_{k+1}, the last one kept
+                if (out.tu && kid == 0) out.tu[(int64_t)i * out.S + pos] = F;
+                #pragma unroll 1
+                for (int j = 0; j < p.Ns; ++j) {
+                    double xi[3];
+                    process_noise(p, (uint32_t)(i * p.Ns + j), su.nid, xi);
+                    em_step(p, su.k0, su.EaR, n, F, h, sqh, xi);
+                }
+                Fprev = F;
+                ++i;
             }
-            if (i == L) break;
-            const double y = z + p.noise_scale * sqrtR *
-                                     normal_first(p.seed, 0, (uint32_t)i, su.nid, kTagMeas);
-            ekf_predict(p, xhat, P, Fprev);
-            ekf_update(p, xhat, P, y);
-            if (!isfinite(P) || !isfinite(xhat)) cnt[C_NONFIN] = 1;
-            if (out.tx && lane == 0) out.tx[(int64_t)i * out.S + pos] = xhat;
-            const bool conv = ms_sqp_lanes(p, N, span, xhat, i, su.istep, su.sign, U, cnt);
-            cnt[C_OCP]++;
-            if (!conv) cnt[C_OCP_FAIL]++;
-            const uint64_t mask = __ballot(lane < N && (U <= p.umin + 1e-6 || U >= p.umax - 1e-6));
-            hsh = fnv1a_step(hsh, (uint32_t)i, mask);
-            const double F = readlane_d(U, 0) / kMlMinPerLs;
-            U = lane_next(U, U, N);   // shift: u_k <- u_{k+1}, the last one kept
-            if (out.tu && lane == 0) out.tu[(int64_t)i * out.S + pos] = F;
-            #pragma unroll 1
-            for (int j = 0; j < p.Ns; ++j) {
-                double xi[3];
-                process_noise(p, (uint32_t)(i * p.Ns + j), su.nid, xi);
-                em_step(p, su.k0, su.EaR, n, F, h, sqh, xi);
-            }
-            Fprev = F;
-        }
-        if (!isfinite(n[0]) || !isfinite(n[1]) || !isfinite(n[2])) cnt[C_NONFIN] = 1;
-        if (lane == 0) {
-            out.phi[pos] = phiacc / (double)(L + 1);
-            out.hash[pos] = hsh;
-            cnt[C_KIND] = 0;
-            cnt[C_N] = N;
-            cnt[C_L] = L;
-            out.flops[pos] = ms_sample_flops(p, N, L, cnt);
+            if (done) {
+                if (!isfinite(n[0]) || !isfinite(n[1]) || !isfinite(n[2])) cnt[C_NONFIN] = 1;
+                if (kid == 0) {
+                    out.phi[pos] = phiacc / (double)(L + 1);
+                    out.hash[pos] = hsh;
+                    cnt[C_KIND] = 0;
+                    cnt[C_N] = N;
+                    cnt[C_L] = L;
+                    out.flops[pos] = ms_sample_flops(p, N, L, cnt);
 #pragma unroll
-            for (int c = 0; c < C_NCNT; ++c) out.cnt[(int64_t)c * out.S + pos] = cnt[c];
+                    for (int c = 0; c < C_NCNT; ++c) out.cnt[(int64_t)c * out.S + pos] = cnt[c];
+                }
+                busy = false;
+            }
         }
     }
 }
