@@ -289,7 +289,9 @@ uint32_t mc_cl_abi_version(void);
  * and PI kernels together, and [1] is -1.                                   
  * mc_cl_plan: launch plan of the NMPC horizon classes, 5 ints per class
  * {NMAX, samples, samples per wavefront, work groups, resident wavefronts};
- * returns the number of classes written (<= max_classes).                   */
+ * with the multiple-shooting NLP a work group is one sample, taken by an
+ * NMAX-lane segment (64 / NMAX per wavefront).  Returns the number of
+ * classes written (<= max_classes).                                         */
 int mc_cl_kernel_ms(mc_cl_ctx *c, float ms[4]);
 int mc_cl_plan(mc_cl_ctx *c, int32_t *out, int max_classes);
 

@@ -1192,7 +1192,7 @@ int mc_cl_plan(mc_cl_ctx* c, int32_t* out, int max_classes) {
         if (n >= max_classes) break;
         out[n * 5 + 0] = k.nmax;
         out[n * 5 + 1] = (int32_t)k.count;
-        out[n * 5 + 2] = k.spw;
+        out[n * 5 + 2] = c->prm.nlp_form == 1 ? 64 / k.nmax : k.spw;
         out[n * 5 + 3] = k.groups;
         out[n * 5 + 4] = k.slots;
         ++n;
