@@ -303,7 +303,7 @@ int mc_cl_plan(mc_cl_ctx *c, int32_t *out, int max_classes);
  * (spw[] reports the value used); for a
  * campaign with want_grad and PI samples, times the PI forward pass with
  * checkpoints plus the reverse pass at each candidate checkpoint interval
- * C (10, 25, 50, 100, 200; those above the longest sample's L skipped,
+ * C (2, 5, 10, 25, 50; those above the longest sample's L skipped,
  * time -1) and keeps the fastest.  Phi and the counters are bitwise the
  * same for every launch shape; C moves the gradient by rounding only (each
  * segment is recomputed from its checkpoint).  Synchronises `hip_stream`; the trial launches overwrite the last

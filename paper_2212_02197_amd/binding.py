@@ -73,7 +73,7 @@ class Stats(C.Structure):
 
 
 TUNE_SPW = (4, 8, 16, 32, 64)
-TUNE_CKPT = (10, 25, 50, 100, 200)
+TUNE_CKPT = (2, 5, 10, 25, 50)
 
 
 class TuneResult(C.Structure):

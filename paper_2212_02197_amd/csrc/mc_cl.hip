@@ -933,7 +933,11 @@ int mc_cl_tune(mc_cl_ctx* c, void* hip_stream, int32_t trial_intervals, mc_cl_tu
     hipStream_t st = (hipStream_t)hip_stream;
     std::memset(r, 0, sizeof(*r));
     static const int kSpw[MC_CL_TUNE_NSPW] = {4, 8, 16, 32, 64};
-    static const int kCk[MC_CL_TUNE_NCK] = {10, 25, 50, 100, 200};
+    // short segments keep the reverse pass's sub-step tape (C Ns 6 doubles
+    // per lane) in the caches between its write and its read back (c2:
+    // reverse pass 33.8 ms at C = 2 against 37.0 ms at C = 10); longer ones
+    // only save checkpoint memory
+    static const int kCk[MC_CL_TUNE_NCK] = {2, 5, 10, 25, 50};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
