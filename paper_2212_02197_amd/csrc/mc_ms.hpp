@@ -871,7 +871,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_MS_WAVES_
             phiacc += (z - zb) * (z - zb);
             if (out.tz && kid == 0) out.tz[(int64_t)i * out.S + pos] = z;
             bool done = false;
-            if (!isfinite(z)) {
+            // (at G = 64 every lane holds the same sample: the branch is
+            // made wavefront-uniform for the compiler, as are N and L)
+            bool zbad = !isfinite(z);
+            if constexpr (G == 64) zbad = uni(zbad ? 1 : 0) != 0;
+            if (zbad) {
                 // the plant diverged (Phi is not a number): no more OCPs
                 cnt[C_NONFIN] = 1;
                 done = true;
