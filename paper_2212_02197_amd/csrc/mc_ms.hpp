@@ -145,16 +145,6 @@ struct DppOps<Aff> {
 __device__ __forceinline__ Aff aff_after(Aff f, Aff g) {
     return Aff{f.a * g.a, fma(f.a, g.b, f.b)};
 }
-__device__ __forceinline__ void scan_affine_suffix(double& a, double& b, int span) {
-    const Aff r = scan_suffix(Aff{a, b}, Aff{1.0, 0.0}, span, aff_after);
-    a = r.a;
-    b = r.b;
-}
-__device__ __forceinline__ void scan_affine_prefix(double& a, double& b, int span) {
-    const Aff r = scan_prefix(Aff{a, b}, Aff{1.0, 0.0}, span, aff_after);
-    a = r.a;
-    b = r.b;
-}
 
 // Linear-fractional maps P -> (m00 P + m01) / (m10 P + m11) as 2x2
 // matrices; a map is unchanged by a scale factor, so each matrix is
@@ -316,7 +306,7 @@ struct Seg {
         return f;
     }
     template <class T, class After>
-    __device__ static __forceinline__ T suffix_rows(T f, T id, After after, bool norm_pairs) {
+    __device__ static __forceinline__ T suffix_rows(T f, T id, After after) {
         const int r = threadIdx.x & 15;
         f = after(f, DppOps<T>::template row<0x101>(f, r <= 14));
         f = after(f, DppOps<T>::template row<0x102>(f, r <= 13));
@@ -328,16 +318,15 @@ struct Seg {
             const T t1 = DppOps<T>::readlane(f, 16), t3 = DppOps<T>::readlane(f, 48);
             f = after(f, row == 0 ? t1 : row == 2 ? t3 : id);
         }
-        (void)norm_pairs;
         return f;
     }
     __device__ static __forceinline__ Aff scan_suffix_aff(Aff f, int span) {
         if constexpr (G == 64) return scan_suffix(f, Aff{1.0, 0.0}, span, aff_after);
-        else return suffix_rows(f, Aff{1.0, 0.0}, aff_after, false);
+        else return suffix_rows(f, Aff{1.0, 0.0}, aff_after);
     }
     __device__ static __forceinline__ Mob scan_suffix_mob(Mob m, int span) {
         if constexpr (G == 64) return scan_mob_suffix(m, span);
-        else return suffix_rows(m, Mob{1.0, 0.0, 0.0, 1.0}, mob_after, true);
+        else return suffix_rows(m, Mob{1.0, 0.0, 0.0, 1.0}, mob_after);
     }
 };
 
