@@ -664,6 +664,21 @@ def test_multiple_shooting_trajectories_and_single_shooting():
     assert ps["n_ocp_fail"][0] == 0
 
 
+def test_multiple_shooting_c3_shape_all_segment_widths():
+    # c3's horizons (16-, 32- and 64-lane segments: four, two and one sample
+    # per wavefront) and ragged lengths 100..400 at full shape, nominal plant
+    # kinetics; segments refill from the queue at different intervals
+    ids = np.arange(5, 100000, 769)[:96]
+    cfg = W.c3_uneven(n_samples=len(ids), sample_ids=ids, sqp_eps=EPS, kin_lognorm_sigma=0.0,
+                      nlp_form=1)
+    phi, stats, ps, _ = gpu_run(cfg)
+    ref = oracle_run(cfg)
+    assert set(ps["N"].tolist()) == {10, 25, 50}
+    assert len(set(ps["L"].tolist())) > 50
+    compare(phi, ps, ref, tag="ms c3 nominal kinetics")
+    check_stats(stats, ref, kinds=(0,))
+
+
 @pytest.mark.parametrize("over", [dict(n_samples=1), dict(L=0), dict(N=1), dict(sqp_max_iter=1),
                                   dict(sqp_max_iter=0), dict(n_samples=65, L=3)])
 def test_multiple_shooting_edge_cases(over):
