@@ -664,6 +664,34 @@ def test_multiple_shooting_trajectories_and_single_shooting():
     assert ps["n_ocp_fail"][0] == 0
 
 
+def test_multiple_shooting_chunked_and_concurrent_classes():
+    # the segmented kernel under chunked graph replays (each chunk a range
+    # of every class's queue) and with the classes on concurrent streams:
+    # bitwise the single sequential launch, on every replay.  Nominal plant
+    # kinetics: with c3's plant-model mismatch one of these 90 samples takes
+    # a W reset the oracle does not (Phi within 8.5e-9), a rounding-sensitive
+    # block near indefiniteness, which is not what this test is about
+    cfg = W.c3_uneven(n_samples=90, sample_id_offset=7000, L_lo=15, L_hi=40, nlp_form=1, sqp_eps=EPS,
+                      kin_lognorm_sigma=0.0)
+    phi1, _, ps1, _ = gpu_run(cfg)
+    assert set(ps1["N"].tolist()) == {10, 25, 50}
+    runs = [gpu_run(dict(cfg, class_streams=1))[::2]]
+    camp = binding.Campaign(dict(cfg, chunk_samples=25))
+    for rep in range(2):
+        camp.run()
+        phi, _ = camp.costs()
+        runs.append((phi, camp.per_sample()))
+        torch.cuda.synchronize()
+    camp.close()
+    for phi, ps in runs:
+        np.testing.assert_array_equal(phi, phi1)
+        np.testing.assert_array_equal(ps["ashash"], ps1["ashash"])
+        for f in binding.CNT_NAMES:
+            np.testing.assert_array_equal(ps[f], ps1[f], err_msg=f)
+    ref = oracle_run(cfg)
+    compare(phi1, ps1, ref, tag="ms chunked classes")
+
+
 def test_multiple_shooting_c3_shape_all_segment_widths():
     # c3's horizons (16-, 32- and 64-lane segments: four, two and one sample
     # per wavefront) and ragged lengths 100..400 at full shape, nominal plant
