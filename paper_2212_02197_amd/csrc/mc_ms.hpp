@@ -488,6 +488,19 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
         const double rmax = fmax(fabs(rxN), S::max(rl));
         const double wd = fmax(fabs(PN * dxN), S::max(wl));
         const double comp = S::sum(act ? tl * nl + tu * nu : 0.0);
+        // the stopping test reads the residuals alone: it comes before the
+        // factorisation, which a converged or capped iterate does not need
+        const double muc = comp * inv2N;
+        if (rmax <= 1e-12 * (1.0 + gsc + wd) && muc <= 1e-14 * (1.0 + gsc)) {
+            iters = it;
+            o = MsQpOut{du, dx, mu, nl, nu};
+            return 0;
+        }
+        if (it == p.ipm_max_iter) {
+            iters = it;
+            o = MsQpOut{du, dx, mu, nl, nu};
+            return 1;
+        }
         // Riccati factor: lane k composes the maps of stages k+1..N-1
         // (divided by R~_k: a slack that has reached 0 in floating point makes
         // R~_k infinite, and the map tends to P -> A_k^2 P + W_{x_k})
@@ -520,17 +533,6 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
         }
         const double e = fma(va, rxN, vb);      // p_{k+1}
         const double kf = -(rt + s.B * e) * hinv;
-        const double muc = comp * inv2N;
-        if (rmax <= 1e-12 * (1.0 + gsc + wd) && muc <= 1e-14 * (1.0 + gsc)) {
-            iters = it;
-            o = MsQpOut{du, dx, mu, nl, nu};
-            return 0;
-        }
-        if (it == p.ipm_max_iter) {
-            iters = it;
-            o = MsQpOut{du, dx, mu, nl, nu};
-            return 1;
-        }
         // forward predictor: affine step and its lengths
         double fa = act ? g : 1.0, fb = act ? s.B * kf : 0.0;
         {

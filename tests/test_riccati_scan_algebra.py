@@ -188,6 +188,9 @@ def scan_ipm(cfg, N, U, A, B, C, FX, WXX, WXU, WUU, maxit):
         rmax = max(abs(rxN), np.abs(ru).max(), np.abs(rx[1:]).max(initial=0.0))
         wd = max(abs(PN * dx[-1]), np.abs(wdu).max(), np.abs(wdx[1:]).max(initial=0.0))
         comp = np.sum(tl * nl + tu * nu)
+        muc = comp / (2.0 * N)
+        if rmax <= 1e-12 * (1 + gsc + wd) and muc <= 1e-14 * (1 + gsc):
+            return du, dx, mu
         m = mobius(A, B, Rt, wxp, wxu)
         m[:, 0] = [1.0, 0.0, 0.0, 1.0]
         sh = np.concatenate([m[:, 1:], np.array([[1.0], [0.0], [0.0], [1.0]])], axis=1)
@@ -201,9 +204,6 @@ def scan_ipm(cfg, N, U, A, B, C, FX, WXX, WXU, WUU, maxit):
         va, vb = suffix_scan_aff(nxt(g, 1.0), nxt(K * rt + rx, 0.0))
         e = va * rxN + vb
         kf = -(rt + B * e) * hinv
-        muc = comp / (2.0 * N)
-        if rmax <= 1e-12 * (1 + gsc + wd) and muc <= 1e-14 * (1 + gsc):
-            return du, dx, mu
         fb = prefix_scan_aff(g.copy(), B * kf)[1]
         dua = K * prev(fb) + kf
         dnla, dnua = -nl - nl * dua / tl, -nu + nu * dua / tu
