@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--nlp-form", type=int, default=0, choices=(0, 1),
                     help="OCP discretisation: 0 single shooting, 1 the paper's multiple shooting")
     ap.add_argument("--eps", type=float, default=0.0, help="SQP KKT tolerance (0: the recipe's)")
+    ap.add_argument("--ckpt", type=int, default=0,
+                    help="PI reverse pass: intervals per checkpoint (0: the tuner's choice)")
     return ap.parse_args()
 
 
@@ -171,6 +173,8 @@ def main():
     cfg = workloads.CONFIGS[args.config](model_nx=args.model_nx, nlp_form=args.nlp_form)
     if args.eps > 0:
         cfg["sqp_eps"] = args.eps
+    if args.ckpt > 0:
+        cfg["ckpt_interval"] = args.ckpt
     if args.samples:
         cfg["n_samples"] = args.samples
         if cfg["kind_split"] >= 0:
