@@ -13,9 +13,11 @@
 //     (convergence).
 // One-state model (the paper's case study).
 //
-// Layout: one sample per wavefront, stage k on lane k (N <= 64).  Every
-// stage quantity of the NLP and of the QP is one register per lane, so the
-// SQP runs without any workspace in memory:
+// Layout: one sample per segment of G lanes, stage k on the segment's lane k
+// (G = 16, 32 or 64 by horizon class: four, two or one sample per
+// wavefront; see Seg below).  Every stage quantity of the NLP and of the QP
+// is one register per lane, so the SQP runs without any workspace in
+// memory:
 //   * the interval maps (values and tangents), the stage costs, the
 //     gradient of the Lagrangian, the block BFGS updates and the
 //     interior point's element-wise steps run on all stages at once, with
@@ -25,7 +27,7 @@
 //     factor P_k is a linear-fractional map of P_{k+1}, composed as 2x2
 //     matrices, and the recursions of the Riccati vector and of the
 //     forward state steps are affine maps;
-//   * sums and maxima over the stages are wavefront reductions.
+//   * sums and maxima over the stages are segment reductions.
 // Only the feasible start of each OCP, where the states follow the inputs
 // through the model, runs the stages one after another.
 //
