@@ -637,6 +637,36 @@ def test_multiple_shooting_paper_horizon_strided():
     check_stats(stats, ref, kinds=(0,))
 
 
+def test_multiple_shooting_paper_scale_full_length():
+    # the benchmark's multiple-shooting workload at full shape: N = 60, 600
+    # intervals with both setpoint changes, 16 strided c1 NMPC ids
+    ids = np.arange(3, 30000, 1873)[:16]
+    cfg = W.c1_paper_scale(n_samples=len(ids), sample_ids=ids, nlp_form=1, sqp_eps=EPS)
+    phi, stats, ps, _ = gpu_run(cfg)
+    ref = oracle_run(cfg)
+    assert (ps["L"] == 600).all() and (ps["kind"] == 0).all()
+    compare(phi, ps, ref, tag="ms c1 full length")
+    check_stats(stats, ref, kinds=(0,))
+
+
+def test_multiple_shooting_c4_mixed_strided_pairs():
+    # c4's shape on the paper's NLP: N = 25 (32-lane segments, two samples
+    # per wavefront), L = 300 with the +-10 % setpoint step, NMPC ids and
+    # the PI samples that share their noise ids.  KKT tolerance 1e-8: the
+    # block BFGS restarts from I at every OCP and gains about one decade of
+    # the KKT measure per 12 iterations here, so at 1e-10 a quarter of these
+    # OCPs run to the 100-iteration cap (1.5 % at 1e-8, the cap rate of the
+    # single-shooting c4 case at 1e-10)
+    nm = np.arange(29, 500000, 7817)[:32]
+    ids = np.concatenate([nm, nm + 500000])
+    cfg = W.c4_mixed(n_samples=len(ids), sample_ids=ids, sqp_eps=1e-8, nlp_form=1)
+    phi, stats, ps, _ = gpu_run(cfg)
+    ref = oracle_run(cfg)
+    assert ps["kind"].tolist() == [0] * 32 + [1] * 32
+    compare(phi, ps, ref, tag="ms c4")
+    check_stats(stats, ref)
+
+
 def test_multiple_shooting_mixed_classes_and_pi():
     # horizons of all three kernel classes with ragged lengths, then PI
     # samples (which do not solve OCPs)
