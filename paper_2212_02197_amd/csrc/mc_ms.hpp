@@ -71,14 +71,16 @@ __device__ __forceinline__ double lane_next(double v, double fill, int n) {
     const double w = dpp_z<0x130>(v);   // wave_shl:1
     return (int)threadIdx.x + 1 < n ? w : fill;
 }
-// A row shift by d (CTRL) of v with bound_ctrl: lanes without a source in
-// the row read `one` when it is set, else 0 (only the high word of 1.0 is
-// not 0).
-template <int CTRL>
-__device__ __forceinline__ double dpp_row(double v, bool has_src, bool one) {
+// A row shift by d (CTRL) of v: lanes without a source in the row read 1.0
+// when ONE is set, else 0.  The low words, and the high word for 0, take
+// bound_ctrl (a lane without a source writes 0); the high word of 1.0 is
+// preset in the destination, which a lane without a source leaves as it is,
+// so no lane mask and no select is needed.
+template <int CTRL, bool ONE>
+__device__ __forceinline__ double dpp_row(double v) {
     const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
-    int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
-    if (one) hi = has_src ? hi : 0x3ff00000;
+    const int hi = ONE ? __builtin_amdgcn_update_dpp(0x3ff00000, __double2hiint(v), CTRL, 0xf, 0xf, false)
+                       : __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 
@@ -94,22 +96,20 @@ template <class T>
 struct DppOps;
 template <class T, class After>
 __device__ __forceinline__ T scan_prefix(T f, T id, int span, After after) {
-    const int r = threadIdx.x & 15;
-    f = after(f, DppOps<T>::template row<0x111>(f, r >= 1));      // row_shr:1
-    if (span > 2) f = after(f, DppOps<T>::template row<0x112>(f, r >= 2));
-    if (span > 4) f = after(f, DppOps<T>::template row<0x114>(f, r >= 4));
-    if (span > 8) f = after(f, DppOps<T>::template row<0x118>(f, r >= 8));
+    f = after(f, DppOps<T>::template row<0x111>(f));      // row_shr:1
+    if (span > 2) f = after(f, DppOps<T>::template row<0x112>(f));
+    if (span > 4) f = after(f, DppOps<T>::template row<0x114>(f));
+    if (span > 8) f = after(f, DppOps<T>::template row<0x118>(f));
     if (span > 16) f = after(f, DppOps<T>::template mov<0x142, 0xa>(id, f));   // row_bcast:15
     if (span > 32) f = after(f, DppOps<T>::template mov<0x143, 0xc>(id, f));   // row_bcast:31
     return f;
 }
 template <class T, class After>
 __device__ __forceinline__ T scan_suffix(T f, T id, int span, After after) {
-    const int r = threadIdx.x & 15;
-    f = after(f, DppOps<T>::template row<0x101>(f, r <= 14));      // row_shl:1
-    if (span > 2) f = after(f, DppOps<T>::template row<0x102>(f, r <= 13));
-    if (span > 4) f = after(f, DppOps<T>::template row<0x104>(f, r <= 11));
-    if (span > 8) f = after(f, DppOps<T>::template row<0x108>(f, r <= 7));
+    f = after(f, DppOps<T>::template row<0x101>(f));      // row_shl:1
+    if (span > 2) f = after(f, DppOps<T>::template row<0x102>(f));
+    if (span > 4) f = after(f, DppOps<T>::template row<0x104>(f));
+    if (span > 8) f = after(f, DppOps<T>::template row<0x108>(f));
     if (span > 16) {
         const int row = threadIdx.x >> 4;
         const T t1 = DppOps<T>::readlane(f, 16);
@@ -137,8 +137,8 @@ struct DppOps<Aff> {
         return Aff{dpp_d<CTRL, ROWMASK>(old.a, v.a), dpp_d<CTRL, ROWMASK>(old.b, v.b)};
     }
     template <int CTRL>
-    __device__ static __forceinline__ Aff row(Aff v, bool has_src) {
-        return Aff{dpp_row<CTRL>(v.a, has_src, true), dpp_row<CTRL>(v.b, has_src, false)};
+    __device__ static __forceinline__ Aff row(Aff v) {
+        return Aff{dpp_row<CTRL, true>(v.a), dpp_row<CTRL, false>(v.b)};
     }
     __device__ static __forceinline__ Aff readlane(Aff v, int l) {
         return Aff{readlane_d(v.a, l), readlane_d(v.b, l)};
@@ -169,17 +169,20 @@ struct DppOps<Mob> {
                    dpp_d<CTRL, ROWMASK>(old.m10, v.m10), dpp_d<CTRL, ROWMASK>(old.m11, v.m11)};
     }
     template <int CTRL>
-    __device__ static __forceinline__ Mob row(Mob v, bool has_src) {
-        return Mob{dpp_row<CTRL>(v.m00, has_src, true), dpp_row<CTRL>(v.m01, has_src, false),
-                   dpp_row<CTRL>(v.m10, has_src, false), dpp_row<CTRL>(v.m11, has_src, true)};
+    __device__ static __forceinline__ Mob row(Mob v) {
+        return Mob{dpp_row<CTRL, true>(v.m00), dpp_row<CTRL, false>(v.m01),
+                   dpp_row<CTRL, false>(v.m10), dpp_row<CTRL, true>(v.m11)};
     }
     __device__ static __forceinline__ Mob readlane(Mob v, int l) {
         return Mob{readlane_d(v.m00, l), readlane_d(v.m01, l), readlane_d(v.m10, l), readlane_d(v.m11, l)};
     }
 };
-// m o g as the matrix product m g (applied to a vector, g acts first); the
-// scan rescales after every second product (the entries of two products of
-// rescaled matrices stay far inside the FP64 range).
+// m o g as the matrix product m g (applied to a vector, g acts first).  A
+// product of k rescaled matrices (largest entry below 1) has entries below
+// 2^(k-1), so the scans rescale only the row totals (16 maps) and the
+// compositions across rows stay far inside the FP64 range.  Rescaling by a
+// power of two is exact and the map is unchanged by it, so where it happens
+// does not change P.
 __device__ __forceinline__ Mob mob_mul(Mob m, Mob g) {
     return Mob{fma(m.m00, g.m00, m.m01 * g.m10), fma(m.m00, g.m01, m.m01 * g.m11),
                fma(m.m10, g.m00, m.m11 * g.m10), fma(m.m10, g.m01, m.m11 * g.m11)};
@@ -193,23 +196,22 @@ __device__ __forceinline__ Mob mob_after_raw(Mob m, Mob g) {
 // Suffix scan: lane k ends with M_k M_{k+1} ....
 __device__ __forceinline__ Mob scan_mob_suffix(Mob m, int span) {
     const Mob id{1.0, 0.0, 0.0, 1.0};
-    const int r = threadIdx.x & 15;
-    m = mob_after_raw(m, DppOps<Mob>::row<0x101>(m, r <= 14));      // row_shl:1
-    if (span > 2) m = mob_after(m, DppOps<Mob>::row<0x102>(m, r <= 13));
-    if (span > 4) m = mob_after_raw(m, DppOps<Mob>::row<0x104>(m, r <= 11));
-    if (span > 8) m = mob_after(m, DppOps<Mob>::row<0x108>(m, r <= 7));
+    m = mob_after_raw(m, DppOps<Mob>::row<0x101>(m));      // row_shl:1
+    if (span > 2) m = mob_after_raw(m, DppOps<Mob>::row<0x102>(m));
+    if (span > 4) m = mob_after_raw(m, DppOps<Mob>::row<0x104>(m));
+    if (span > 8) m = mob_after(m, DppOps<Mob>::row<0x108>(m));
     if (span > 16) {
         const int row = threadIdx.x >> 4;
         const Mob t1 = DppOps<Mob>::readlane(m, 16);
         Mob s = t1;
         if (span > 32) {
             const Mob t3 = DppOps<Mob>::readlane(m, 48);
-            const Mob s2 = mob_after(DppOps<Mob>::readlane(m, 32), t3);
-            s = row == 0 ? mob_after(t1, s2) : row == 1 ? s2 : row == 2 ? t3 : id;
+            const Mob s2 = mob_after_raw(DppOps<Mob>::readlane(m, 32), t3);
+            s = row == 0 ? mob_after_raw(t1, s2) : row == 1 ? s2 : row == 2 ? t3 : id;
         } else {
             s = row == 0 ? t1 : id;
         }
-        m = mob_after(m, s);
+        m = mob_after_raw(m, s);
     }
     return m;
 }
@@ -299,21 +301,19 @@ struct Seg {
     __device__ static __forceinline__ Aff scan_prefix_aff(Aff f, int span) {
         const Aff id{1.0, 0.0};
         if constexpr (G == 64) return scan_prefix(f, id, span, aff_after);
-        const int r = threadIdx.x & 15;
-        f = aff_after(f, DppOps<Aff>::row<0x111>(f, r >= 1));
-        f = aff_after(f, DppOps<Aff>::row<0x112>(f, r >= 2));
-        f = aff_after(f, DppOps<Aff>::row<0x114>(f, r >= 4));
-        f = aff_after(f, DppOps<Aff>::row<0x118>(f, r >= 8));
+        f = aff_after(f, DppOps<Aff>::row<0x111>(f));
+        f = aff_after(f, DppOps<Aff>::row<0x112>(f));
+        f = aff_after(f, DppOps<Aff>::row<0x114>(f));
+        f = aff_after(f, DppOps<Aff>::row<0x118>(f));
         if constexpr (G == 32) f = aff_after(f, DppOps<Aff>::mov<0x142, 0xa>(id, f));   // row_bcast:15
         return f;
     }
     template <class T, class After>
     __device__ static __forceinline__ T suffix_rows(T f, T id, After after) {
-        const int r = threadIdx.x & 15;
-        f = after(f, DppOps<T>::template row<0x101>(f, r <= 14));
-        f = after(f, DppOps<T>::template row<0x102>(f, r <= 13));
-        f = after(f, DppOps<T>::template row<0x104>(f, r <= 11));
-        f = after(f, DppOps<T>::template row<0x108>(f, r <= 7));
+        f = after(f, DppOps<T>::template row<0x101>(f));
+        f = after(f, DppOps<T>::template row<0x102>(f));
+        f = after(f, DppOps<T>::template row<0x104>(f));
+        f = after(f, DppOps<T>::template row<0x108>(f));
         if constexpr (G == 32) {
             // row 0 composes with row 1's total (lane 16), row 2 with row 3's (lane 48)
             const int row = threadIdx.x >> 4;
@@ -328,7 +328,21 @@ struct Seg {
     }
     __device__ static __forceinline__ Mob scan_suffix_mob(Mob m, int span) {
         if constexpr (G == 64) return scan_mob_suffix(m, span);
-        else return suffix_rows(m, Mob{1.0, 0.0, 0.0, 1.0}, mob_after);
+        if constexpr (G == 16) {
+            m = mob_after_raw(m, DppOps<Mob>::row<0x101>(m));
+            m = mob_after_raw(m, DppOps<Mob>::row<0x102>(m));
+            m = mob_after_raw(m, DppOps<Mob>::row<0x104>(m));
+            return mob_after_raw(m, DppOps<Mob>::row<0x108>(m));
+        } else {
+            m = mob_after_raw(m, DppOps<Mob>::row<0x101>(m));
+            m = mob_after_raw(m, DppOps<Mob>::row<0x102>(m));
+            m = mob_after_raw(m, DppOps<Mob>::row<0x104>(m));
+            m = mob_after(m, DppOps<Mob>::row<0x108>(m));
+            // row 0 composes with row 1's total (lane 16), row 2 with row 3's (lane 48)
+            const int row = threadIdx.x >> 4;
+            const Mob t1 = DppOps<Mob>::readlane(m, 16), t3 = DppOps<Mob>::readlane(m, 48);
+            return mob_after_raw(m, row == 0 ? t1 : row == 2 ? t3 : Mob{1.0, 0.0, 0.0, 1.0});
+        }
     }
 };
 
