@@ -84,8 +84,9 @@ __device__ __forceinline__ double dpp_row(double v) {
     return __hiloint2double(hi, lo);
 }
 
-// Inclusive scans over lanes 0..span-1 (span a power of two, <= 64) of
-// maps composed by `after(f, g)` = f o g.  Prefix: lane k ends with
+// Inclusive scans over the 64 lanes of the wavefront of maps composed by
+// `after(f, g)` = f o g (lanes past a sample's stages carry the identity, so
+// a scan over all lanes is exact for any horizon).  Prefix: lane k ends with
 // f_k o f_{k-1} o ... o f_0; suffix: lane k ends with f_k o f_{k+1} o ....
 // Within each 16-lane row the scan takes row shifts by 1, 2, 4 and 8
 // (lanes without a source in the row compose with the identity).  Across
@@ -95,33 +96,26 @@ __device__ __forceinline__ double dpp_row(double v) {
 template <class T>
 struct DppOps;
 template <class T, class After>
-__device__ __forceinline__ T scan_prefix(T f, T id, int span, After after) {
+__device__ __forceinline__ T scan_prefix(T f, T id, After after) {
     f = after(f, DppOps<T>::template row<0x111>(f));      // row_shr:1
-    if (span > 2) f = after(f, DppOps<T>::template row<0x112>(f));
-    if (span > 4) f = after(f, DppOps<T>::template row<0x114>(f));
-    if (span > 8) f = after(f, DppOps<T>::template row<0x118>(f));
-    if (span > 16) f = after(f, DppOps<T>::template mov<0x142, 0xa>(id, f));   // row_bcast:15
-    if (span > 32) f = after(f, DppOps<T>::template mov<0x143, 0xc>(id, f));   // row_bcast:31
+    f = after(f, DppOps<T>::template row<0x112>(f));
+    f = after(f, DppOps<T>::template row<0x114>(f));
+    f = after(f, DppOps<T>::template row<0x118>(f));
+    f = after(f, DppOps<T>::template mov<0x142, 0xa>(id, f));   // row_bcast:15
+    f = after(f, DppOps<T>::template mov<0x143, 0xc>(id, f));   // row_bcast:31
     return f;
 }
 template <class T, class After>
-__device__ __forceinline__ T scan_suffix(T f, T id, int span, After after) {
+__device__ __forceinline__ T scan_suffix(T f, T id, After after) {
     f = after(f, DppOps<T>::template row<0x101>(f));      // row_shl:1
-    if (span > 2) f = after(f, DppOps<T>::template row<0x102>(f));
-    if (span > 4) f = after(f, DppOps<T>::template row<0x104>(f));
-    if (span > 8) f = after(f, DppOps<T>::template row<0x108>(f));
-    if (span > 16) {
+    f = after(f, DppOps<T>::template row<0x102>(f));
+    f = after(f, DppOps<T>::template row<0x104>(f));
+    f = after(f, DppOps<T>::template row<0x108>(f));
+    {
         const int row = threadIdx.x >> 4;
-        const T t1 = DppOps<T>::readlane(f, 16);
-        T s = t1;   // rows after row 0 (of 2)
-        if (span > 32) {
-            const T t3 = DppOps<T>::readlane(f, 48);
-            const T s2 = after(DppOps<T>::readlane(f, 32), t3);   // rows 2..3
-            s = row == 0 ? after(t1, s2) : row == 1 ? s2 : row == 2 ? t3 : id;
-        } else {
-            s = row == 0 ? t1 : id;
-        }
-        f = after(f, s);
+        const T t1 = DppOps<T>::readlane(f, 16), t3 = DppOps<T>::readlane(f, 48);
+        const T s2 = after(DppOps<T>::readlane(f, 32), t3);   // rows 2..3
+        f = after(f, row == 0 ? after(t1, s2) : row == 1 ? s2 : row == 2 ? t3 : id);
     }
     return f;
 }
@@ -194,26 +188,16 @@ __device__ __forceinline__ Mob mob_after_raw(Mob m, Mob g) {
     return mob_mul(m, g);
 }
 // Suffix scan: lane k ends with M_k M_{k+1} ....
-__device__ __forceinline__ Mob scan_mob_suffix(Mob m, int span) {
+__device__ __forceinline__ Mob scan_mob_suffix(Mob m) {
     const Mob id{1.0, 0.0, 0.0, 1.0};
     m = mob_after_raw(m, DppOps<Mob>::row<0x101>(m));      // row_shl:1
-    if (span > 2) m = mob_after_raw(m, DppOps<Mob>::row<0x102>(m));
-    if (span > 4) m = mob_after_raw(m, DppOps<Mob>::row<0x104>(m));
-    if (span > 8) m = mob_after(m, DppOps<Mob>::row<0x108>(m));
-    if (span > 16) {
-        const int row = threadIdx.x >> 4;
-        const Mob t1 = DppOps<Mob>::readlane(m, 16);
-        Mob s = t1;
-        if (span > 32) {
-            const Mob t3 = DppOps<Mob>::readlane(m, 48);
-            const Mob s2 = mob_after_raw(DppOps<Mob>::readlane(m, 32), t3);
-            s = row == 0 ? mob_after_raw(t1, s2) : row == 1 ? s2 : row == 2 ? t3 : id;
-        } else {
-            s = row == 0 ? t1 : id;
-        }
-        m = mob_after_raw(m, s);
-    }
-    return m;
+    m = mob_after_raw(m, DppOps<Mob>::row<0x102>(m));
+    m = mob_after_raw(m, DppOps<Mob>::row<0x104>(m));
+    m = mob_after(m, DppOps<Mob>::row<0x108>(m));
+    const int row = threadIdx.x >> 4;
+    const Mob t1 = DppOps<Mob>::readlane(m, 16), t3 = DppOps<Mob>::readlane(m, 48);
+    const Mob s2 = mob_after_raw(DppOps<Mob>::readlane(m, 32), t3);
+    return mob_after_raw(m, row == 0 ? mob_after_raw(t1, s2) : row == 1 ? s2 : row == 2 ? t3 : id);
 }
 
 // ------------------------------------------------------------ segments ---
@@ -298,9 +282,9 @@ struct Seg {
         else return (m >> base()) & ((1ull << G) - 1);
     }
     // inclusive prefix / suffix scans of affine maps inside the segment
-    __device__ static __forceinline__ Aff scan_prefix_aff(Aff f, int span) {
+    __device__ static __forceinline__ Aff scan_prefix_aff(Aff f) {
         const Aff id{1.0, 0.0};
-        if constexpr (G == 64) return scan_prefix(f, id, span, aff_after);
+        if constexpr (G == 64) return scan_prefix(f, id, aff_after);
         f = aff_after(f, DppOps<Aff>::row<0x111>(f));
         f = aff_after(f, DppOps<Aff>::row<0x112>(f));
         f = aff_after(f, DppOps<Aff>::row<0x114>(f));
@@ -322,12 +306,12 @@ struct Seg {
         }
         return f;
     }
-    __device__ static __forceinline__ Aff scan_suffix_aff(Aff f, int span) {
-        if constexpr (G == 64) return scan_suffix(f, Aff{1.0, 0.0}, span, aff_after);
+    __device__ static __forceinline__ Aff scan_suffix_aff(Aff f) {
+        if constexpr (G == 64) return scan_suffix(f, Aff{1.0, 0.0}, aff_after);
         else return suffix_rows(f, Aff{1.0, 0.0}, aff_after);
     }
-    __device__ static __forceinline__ Mob scan_suffix_mob(Mob m, int span) {
-        if constexpr (G == 64) return scan_mob_suffix(m, span);
+    __device__ static __forceinline__ Mob scan_suffix_mob(Mob m) {
+        if constexpr (G == 64) return scan_mob_suffix(m);
         if constexpr (G == 16) {
             m = mob_after_raw(m, DppOps<Mob>::row<0x101>(m));
             m = mob_after_raw(m, DppOps<Mob>::row<0x102>(m));
@@ -453,7 +437,7 @@ struct MsQpOut {
 };
 
 template <int G>
-__device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, MsStage s,
+__device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, MsStage s,
                                         MsQpOut& o, int& iters) {
     using S = Seg<G>;
     const int lane = S::k();   // the stage of this lane
@@ -473,7 +457,7 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
         if (du > hi - dl) du = hi - dl;
         double a = act ? s.A : 1.0, b = act ? fma(s.B, du, s.C) : 0.0;
         {
-            const Aff r = S::scan_prefix_aff(Aff{a, b}, span);
+            const Aff r = S::scan_prefix_aff(Aff{a, b});
             a = r.a;
             b = r.b;
         }
@@ -528,7 +512,7 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
         }
         m = Mob{S::next(m.m00, 1.0, N), S::next(m.m01, 0.0, N), S::next(m.m10, 0.0, N),
                 S::next(m.m11, 1.0, N)};
-        m = S::scan_suffix_mob(mob_norm(m), span);
+        m = S::scan_suffix_mob(mob_norm(m));
         const double Pn = (m.m00 * PN + m.m01) * rcp_nr(m.m10 * PN + m.m11);   // P_{k+1}
         const double Huu = Rt + s.B * s.B * Pn;
         if (S::any(act && !(Huu > 0.0))) {
@@ -543,7 +527,7 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
         va = S::next(va, 1.0, N);
         vb = S::next(vb, 0.0, N);
         {
-            const Aff r = S::scan_suffix_aff(Aff{va, vb}, span);
+            const Aff r = S::scan_suffix_aff(Aff{va, vb});
             va = r.a;
             vb = r.b;
         }
@@ -552,7 +536,7 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
         // forward predictor: affine step and its lengths
         double fa = act ? g : 1.0, fb = act ? s.B * kf : 0.0;
         {
-            const Aff r = S::scan_prefix_aff(Aff{fa, fb}, span);
+            const Aff r = S::scan_prefix_aff(Aff{fa, fb});
             fa = r.a;
             fb = r.b;
         }
@@ -582,7 +566,7 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
         ca = S::next(ca, 1.0, N);
         cb = S::next(cb, 0.0, N);
         {
-            const Aff r = S::scan_suffix_aff(Aff{ca, cb}, span);
+            const Aff r = S::scan_suffix_aff(Aff{ca, cb});
             ca = r.a;
             cb = r.b;
         }
@@ -590,7 +574,7 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, int span, 
         const double kf2 = -(rt2 + s.B * e2) * hinv;
         double ga = act ? g : 1.0, gb = act ? s.B * kf2 : 0.0;
         {
-            const Aff r = S::scan_prefix_aff(Aff{ga, gb}, span);
+            const Aff r = S::scan_prefix_aff(Aff{ga, gb});
             ga = r.a;
             gb = r.b;
         }
@@ -628,7 +612,7 @@ struct MsNlp {
 // The SQP of one OCP from x-hat (x0) with the warm-started inputs in U;
 // returns true if the KKT test passed (else the last iterate stands).
 template <int G>
-__device__ __forceinline__ bool ms_sqp_lanes(const DevParams& p, int N, int span, double x0,
+__device__ __forceinline__ bool ms_sqp_lanes(const DevParams& p, int N, double x0,
                                              int i0, int istep, double sign, double& Uio,
                                              int (&cnt)[C_NCNT]) {
     using S = Seg<G>;
@@ -708,7 +692,7 @@ __device__ __forceinline__ bool ms_sqp_lanes(const DevParams& p, int N, int span
                 v.WUU = 1.0;
             }
             int it = 0;
-            st = ms_qp_lanes<G>(p, N, span, MsStage{v.U, v.A, v.B, v.C, v.FX, v.WXX, v.WXU, v.WUU}, q, it);
+            st = ms_qp_lanes<G>(p, N, MsStage{v.U, v.A, v.B, v.C, v.FX, v.WXX, v.WXU, v.WUU}, q, it);
             cnt[C_IPM] += it;
             if (st != -1 || reset) break;
             reset = true;
@@ -831,7 +815,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_MS_WAVES_
     bool busy = false, drained = false;
     int64_t pos = 0;
     Setup su{};
-    int N = 1, L = 0, i = 0, span = G;
+    int N = 1, L = 0, i = 0;
     int cnt[C_NCNT];
     double n[3] = {0.0, 0.0, 0.0};
     double xhat = 0.0, P = 0.0, Fprev = 0.0, phiacc = 0.0, U = 0.0;
@@ -853,10 +837,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_MS_WAVES_
                 N = G == 64 ? uni(su.N) : su.N;
                 L = G == 64 ? uni(su.L) : su.L;
                 i = 0;
-                if (G == 64) {
-                    span = 1;
-                    while (span < N) span <<= 1;
-                }
 #pragma unroll
                 for (int c = 0; c < C_NCNT; ++c) cnt[c] = 0;
                 n[0] = su.n0[0];
@@ -895,7 +875,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_MS_WAVES_
                 ekf_update(p, xhat, P, y);
                 if (!isfinite(P) || !isfinite(xhat)) cnt[C_NONFIN] = 1;
                 if (out.tx && kid == 0) out.tx[(int64_t)i * out.S + pos] = xhat;
-                const bool conv = ms_sqp_lanes<G>(p, N, span, xhat, i, su.istep, su.sign, U, cnt);
+                const bool conv = ms_sqp_lanes<G>(p, N, xhat, i, su.istep, su.sign, U, cnt);
                 cnt[C_OCP]++;
                 if (!conv) cnt[C_OCP_FAIL]++;
                 const uint64_t mask = S::mask(kid < N && (U <= p.umin + 1e-6 || U >= p.umax - 1e-6));
