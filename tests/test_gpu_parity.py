@@ -737,6 +737,23 @@ def test_multiple_shooting_c3_shape_all_segment_widths():
     check_stats(stats, ref, kinds=(0,))
 
 
+def test_multiple_shooting_diverged_plant_stays_in_its_segment():
+    # the diverging c3 sample of test_diverged_plant_ends_the_closed_loop
+    # (id 1937, N = 10) on the paper's NLP: its 16-lane segment shares a
+    # wavefront with the segments of the two other N = 10 samples, which
+    # must not see its non-finite values; the closed loop stops on both
+    # sides alike
+    ids = np.array([1936, 1937, 1938, 1939])
+    cfg = W.c3_uneven(n_samples=len(ids), sample_ids=ids, sqp_eps=EPS, nlp_form=1)
+    phi, stats, ps, _ = gpu_run(cfg)
+    ref = oracle_run(cfg)
+    assert ps["N"].tolist() == [10, 10, 10, 25]
+    assert np.isnan(phi[1]) and ps["nonfinite"][1] == 1 and ps["n_ocp"][1] < ps["L"][1]
+    compare(phi, ps, ref, tag="ms diverged plant")
+    check_stats(stats, ref, kinds=(0,))
+    assert stats["count"][0] == 3
+
+
 @pytest.mark.parametrize("over", [dict(n_samples=1), dict(L=0), dict(N=1), dict(sqp_max_iter=1),
                                   dict(sqp_max_iter=0), dict(n_samples=65, L=3)])
 def test_multiple_shooting_edge_cases(over):
