@@ -91,6 +91,41 @@ hipError_t launch_nmpc(const DevParams& dp, const NmpcWork& wk, const Outs& o, i
     return hipGetLastError();
 }
 
+// Lanes per PI sample (1, 2 or 4; see pi_kernel): the most for which the
+// launch keeps at most one wavefront per SIMD (four per compute unit), so
+// that wider groups shorten each wavefront's serial chain without queueing
+// wavefronts behind one another.  The results do not depend on it.
+int pi_lanes(int64_t n, int n_cu) {
+    const int64_t simds = 4 * (int64_t)std::max(n_cu, 1);
+    for (int k = 4; k > 1; k >>= 1)
+        if ((n * k + 63) / 64 <= simds) return k;
+    return 1;
+}
+// The PI forward pass over n samples (a chunk's with ctl, else the first n
+// of pos).
+hipError_t launch_pi(int n_cu, int64_t n, hipStream_t st, const DevParams& dp, const int64_t* pos,
+                     int64_t npi, const Outs& o, double* ck, const int* ctl, int64_t ppc) {
+    const int k = pi_lanes(n, n_cu);
+    const dim3 grid((unsigned)((n * k + 63) / 64)), block(64);
+    if (k == 4) hipLaunchKernelGGL(pi_kernel<4>, grid, block, 0, st, dp, pos, npi, o, ck, ctl, ppc);
+    else if (k == 2) hipLaunchKernelGGL(pi_kernel<2>, grid, block, 0, st, dp, pos, npi, o, ck, ctl, ppc);
+    else hipLaunchKernelGGL(pi_kernel<1>, grid, block, 0, st, dp, pos, npi, o, ck, ctl, ppc);
+    return hipGetLastError();
+}
+hipError_t launch_pi_reverse(int n_cu, hipStream_t st, const DevParams& dp, const int64_t* pos,
+                             int64_t npi, const double* ck, double* tape, double* ivtape,
+                             double* gk) {
+    const int k = pi_lanes(npi, n_cu);
+    const dim3 grid((unsigned)((npi * k + 63) / 64)), block(64);
+    if (k == 4)
+        hipLaunchKernelGGL(pi_reverse_kernel<4>, grid, block, 0, st, dp, pos, npi, ck, tape, ivtape, gk);
+    else if (k == 2)
+        hipLaunchKernelGGL(pi_reverse_kernel<2>, grid, block, 0, st, dp, pos, npi, ck, tape, ivtape, gk);
+    else
+        hipLaunchKernelGGL(pi_reverse_kernel<1>, grid, block, 0, st, dp, pos, npi, ck, tape, ivtape, gk);
+    return hipGetLastError();
+}
+
 // Multiple shooting: the horizon class NMAX is the segment width (samples
 // per wavefront 64 / NMAX).
 template <int G>
@@ -520,10 +555,8 @@ static int launch_step(mc_cl_ctx* c, hipStream_t st, const Outs& out, bool chunk
     if (ev_mid) HIPCHK(hipEventRecord(ev_mid, st));
     if (c->n_pi) {
         const int64_t n = chunk ? c->pi_per_chunk : c->n_pi;
-        hipLaunchKernelGGL(pi_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, c->dp,
-                           c->d_pos_pi, c->n_pi, out, c->d_ck, chunk ? c->d_ctl : nullptr,
-                           c->pi_per_chunk);
-        HIPCHK(hipGetLastError());
+        HIPCHK(launch_pi(c->n_cu, n, st, c->dp, c->d_pos_pi, c->n_pi, out, c->d_ck,
+                         chunk ? c->d_ctl : nullptr, c->pi_per_chunk));
     }
     if (chunk) {
         hipLaunchKernelGGL(chunk_end, dim3(1), dim3(64), 0, st, c->d_ctl);
@@ -880,9 +913,8 @@ int mc_cl_grad(mc_cl_ctx* c, void* hip_stream, double g[2], double* per_sample) 
     HIPCHK(hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)hip_stream;
     HIPCHK(hipEventRecord(c->ev[4], st));
-    hipLaunchKernelGGL(pi_reverse_kernel, dim3((unsigned)((c->n_pi + 63) / 64)), dim3(64), 0, st,
-                       c->dp, c->d_pos_pi, c->n_pi, c->d_ck, c->d_tape, c->d_ivtape, c->d_gk);
-    HIPCHK(hipGetLastError());
+    HIPCHK(launch_pi_reverse(c->n_cu, st, c->dp, c->d_pos_pi, c->n_pi, c->d_ck, c->d_tape,
+                             c->d_ivtape, c->d_gk));
     hipLaunchKernelGGL(grad_reduce_kernel, dim3(1), dim3(1024), 0, st, c->d_gk, c->n_pi, c->d_gsum);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(c->ev[5], st));
@@ -1006,13 +1038,10 @@ int mc_cl_tune(mc_cl_ctx* c, void* hip_stream, int32_t trial_intervals, mc_cl_tu
             if ((rc = size_ckpt(c, kCk[j])) != MC_CL_OK) break;
             float ms = 0.0f;
             rc = timed([&]() -> int {
-                const unsigned nb = (unsigned)((c->n_pi + 63) / 64);
-                hipLaunchKernelGGL(pi_kernel, dim3(nb), dim3(64), 0, st, c->dp, c->d_pos_pi,
-                                   c->n_pi, out, c->d_ck, nullptr, (int64_t)0);
-                HIPCHK(hipGetLastError());
-                hipLaunchKernelGGL(pi_reverse_kernel, dim3(nb), dim3(64), 0, st, c->dp,
-                                   c->d_pos_pi, c->n_pi, c->d_ck, c->d_tape, c->d_ivtape, c->d_gk);
-                HIPCHK(hipGetLastError());
+                HIPCHK(launch_pi(c->n_cu, c->n_pi, st, c->dp, c->d_pos_pi, c->n_pi, out, c->d_ck,
+                                 nullptr, (int64_t)0));
+                HIPCHK(launch_pi_reverse(c->n_cu, st, c->dp, c->d_pos_pi, c->n_pi, c->d_ck,
+                                         c->d_tape, c->d_ivtape, c->d_gk));
                 return MC_CL_OK;
             }, ms);
             r->grad_ms[j] = ms;
@@ -1182,9 +1211,8 @@ int mc_cl_run_static(const mc_cl_params* p, void* hip_stream, const mc_cl_output
         off += count;
     }
     if (counts[3] > 0) {
-        hipLaunchKernelGGL(pi_kernel, dim3((unsigned)((counts[3] + 63) / 64)), dim3(64), 0, st, dp,
-                           d_pos + off, (int64_t)counts[3], out, nullptr, nullptr, (int64_t)0);
-        HIPCHK(hipGetLastError());
+        HIPCHK(launch_pi(n_cu, (int64_t)counts[3], st, dp, d_pos + off, (int64_t)counts[3], out,
+                         nullptr, nullptr, (int64_t)0));
     }
     return MC_CL_OK;
 }

@@ -1,7 +1,8 @@
 // mc_kernels.hpp -- closed-loop kernels of the Monte Carlo CSTR campaign
 // (arXiv 2212.02197) for gfx950.
 //
-//  * pi_kernel: one sample per lane, the whole closed loop in registers.
+//  * pi_kernel: one sample per group of K lanes (K = 1, 2 or 4), the whole
+//    closed loop in registers.
 //  * nmpc_kernel: persistent; each 64-lane wavefront pulls groups of `spw`
 //    samples from a device work queue and runs their closed loops.  Scalar
 //    serial work (plant, estimator, RK4 shooting, gradient, line search, KKT
@@ -843,9 +844,54 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NMAX == 64 ?
 // state (n, I-hat) at the start of every interval i = 0, C, 2C, ... is kept
 // for the reverse pass: ck[((i / C) * 4 + f) * npi + t].  With ctl != null
 // the launch covers the PI samples [c ppc, (c + 1) ppc) of chunk c = *ctl.
+// K lanes per PI sample.  A PI closed loop is one serial chain, so a launch
+// with fewer wavefronts than SIMDs takes one chain's time, and most of a
+// sub-step's instructions draw its noise (Philox, Box-Muller), which does
+// not depend on the state.  The K lanes of a group draw the noise of K
+// sub-steps at once, lane r that of sub-step j0 + r, and then all of them
+// integrate the K sub-steps in turn, each taking a sub-step's normals from
+// the lane that drew them by a DPP quad broadcast.  The lanes of a group
+// compute the same values in the same order, so they hold the same state
+// bit for bit (the results do not depend on K) and write the same outputs
+// to the same addresses; every lane reads back only what it wrote itself.
+template <int K, int RR>
+__device__ __forceinline__ double group_bcast(double v) {
+    static_assert((K == 1 || K == 2 || K == 4) && RR < K, "groups of 1, 2 or 4 lanes");
+    if constexpr (K == 1) return v;
+    else if constexpr (K == 2) return dpp_z<RR | RR << 2 | (2 + RR) << 4 | (2 + RR) << 6>(v);
+    else return dpp_z<RR * 0x55>(v);   // quad_perm [RR, RR, RR, RR]
+}
+template <int K, int RR, class Step>
+__device__ __forceinline__ void pi_group_steps(int j0, int Ns, const double (&own)[3], Step& step) {
+    if constexpr (RR < K) {
+        // j0 and Ns are the same on every lane: the broadcast runs on the
+        // whole group
+        if (j0 + RR < Ns) {
+            const double xi[3] = {group_bcast<K, RR>(own[0]), group_bcast<K, RR>(own[1]),
+                                  group_bcast<K, RR>(own[2])};
+            step(j0 + RR, xi);
+        }
+        pi_group_steps<K, RR + 1>(j0, Ns, own, step);
+    }
+}
+// The Ns Euler-Maruyama sub-steps of interval i, K at a time; step(j, xi)
+// takes sub-step j with its noise.  A lane whose sub-step index passes Ns
+// draws a noise value nobody uses.
+template <int K, class Step>
+__device__ __forceinline__ void pi_substeps(const DevParams& p, const Setup& su, int i, Step step) {
+    const int r = (int)threadIdx.x & (K - 1);
+    #pragma unroll 1
+    for (int j0 = 0; j0 < p.Ns; j0 += K) {
+        double own[3];
+        process_noise(p, (uint32_t)(i * p.Ns + j0 + r), su.nid, own);
+        pi_group_steps<K, 0>(j0, p.Ns, own, step);
+    }
+}
+
+template <int K>
 __global__ __launch_bounds__(64) void pi_kernel(DevParams p, const int64_t* pos_list, int64_t npi,
                                                 Outs out, double* ck, const int* ctl, int64_t ppc) {
-    int64_t t1 = npi, t = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    int64_t t1 = npi, t = ((int64_t)blockIdx.x * 64 + threadIdx.x) / K;
     if (ctl) {
         const int64_t t0 = (int64_t)(*ctl) * ppc;
         t += t0;
@@ -911,12 +957,8 @@ __global__ __launch_bounds__(64) void pi_kernel(DevParams p, const int64_t* pos_
         Ihat = Ik + p.Ts * p.kaw * (uh - uk);
         const double F = uk;
         if (out.tu) out.tu[(int64_t)i * out.S + pos] = F;
-        #pragma unroll 1
-        for (int j = 0; j < p.Ns; ++j) {
-            double xi[3];
-            process_noise(p, (uint32_t)(i * p.Ns + j), su.nid, xi);
-            em_step(p, su.k0, su.EaR, n, F, h, sqh, xi);
-        }
+        auto step = [&](int, const double (&xi)[3]) { em_step(p, su.k0, su.EaR, n, F, h, sqh, xi); };
+        pi_substeps<K>(p, su, i, step);
         Fprev = F;
     }
     if (!isfinite(n[0]) || !isfinite(n[1]) || !isfinite(n[2])) nonfin = 1;
@@ -935,12 +977,15 @@ __global__ __launch_bounds__(64) void pi_kernel(DevParams p, const int64_t* pos_
 // instead of taping it halves the tape but adds two Philox blocks and a
 // Box-Muller pair to each lane's serial chain: c2's reverse pass took
 // 48.9 ms that way against 35.1 ms taped.)  Writes dPhi/dkP and dPhi/dkI
-// per sample.
+// per sample.  A sample takes K lanes as in pi_kernel: the recomputation
+// draws the noise of K sub-steps at once, and the K lanes tape, sweep and
+// write the same values.
+template <int K>
 __global__ __launch_bounds__(64) void pi_reverse_kernel(DevParams p, const int64_t* pos_list,
                                                         int64_t npi, const double* ck,
                                                         double* tape, double* iv_tape,
                                                         double* gk /* [2][npi] */) {
-    const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int64_t t = ((int64_t)blockIdx.x * 64 + threadIdx.x) / K;
     if (t >= npi) return;
     const int64_t pos = pos_list[t];
     const Setup su = sample_setup(pos);
@@ -983,10 +1028,7 @@ __global__ __launch_bounds__(64) void pi_reverse_kernel(DevParams p, const int64
             if (uk > p.pi_umax) uk = p.pi_umax;
             if (uk < p.pi_umin) uk = p.pi_umin;
             Ihat = Ik + p.Ts * p.kaw * (uh - uk);
-            #pragma unroll 1
-            for (int j = 0; j < p.Ns; ++j) {
-                double xi[3];
-                process_noise(p, (uint32_t)(i * p.Ns + j), su.nid, xi);
+            auto step = [&](int j, const double (&xi)[3]) {
                 const int64_t st = (int64_t)li * p.Ns + j;
                 tape[(st * 6 + 0) * npi + t] = n[0];
                 tape[(st * 6 + 1) * npi + t] = n[1];
@@ -995,7 +1037,8 @@ __global__ __launch_bounds__(64) void pi_reverse_kernel(DevParams p, const int64
                 tape[(st * 6 + 4) * npi + t] = xi[1];
                 tape[(st * 6 + 5) * npi + t] = xi[2];
                 em_step(p, su.k0, su.EaR, n, uk, h, sqh, xi);
-            }
+            };
+            pi_substeps<K>(p, su, i, step);
         }
         if (!have_final) {
             // cost term of the last sample point t_L
