@@ -353,6 +353,33 @@ def test_pi_gradient_against_oracle_tangent():
     assert g[1] == pytest.approx(mean_ref[1], rel=1e-9)
 
 
+def test_pi_lanes_per_sample_do_not_change_results():
+    # a PI campaign gives each sample 4, 2 or 1 lanes, the most that keep its
+    # wavefronts at one per SIMD; planning for fewer compute units forces
+    # each width on the same 640 samples (all CUs: 4 lanes, 40 wavefronts;
+    # 8 CUs, 32 SIMDs: 2 lanes; 4 CUs, 16 SIMDs: 1 lane).  Costs,
+    # trajectories and gradients are bitwise the same.
+    cfg = W.c2_pi_adjoint(n_samples=640, L=60)
+    runs = []
+    for cu in (0, 8, 4):
+        camp = binding.Campaign(dict(cfg, cu_limit=cu))
+        camp.run(trajectories=True)
+        phi, _ = camp.costs()
+        g, gs = camp.grad(per_sample=True)
+        tr = {k: v.cpu().numpy() for k, v in camp.traj.items()}
+        runs.append((phi, np.asarray(g), gs.cpu().numpy(), tr))
+        camp.close()
+    phi0, g0, gs0, tr0 = runs[0]
+    for phi, g, gs, tr in runs[1:]:
+        np.testing.assert_array_equal(phi, phi0)
+        np.testing.assert_array_equal(g, g0)
+        np.testing.assert_array_equal(gs, gs0)
+        for k in tr0:
+            np.testing.assert_array_equal(tr[k], tr0[k], err_msg=k)
+    ref = oracle_run(cfg)
+    assert (np.abs(phi0 - ref["phi"]) / ref["phi"]).max() <= 1e-9
+
+
 def test_launch_shape_does_not_change_results():
     cfg = W.c0_small_nmpc(n_samples=50, L=8)
     outs = []
