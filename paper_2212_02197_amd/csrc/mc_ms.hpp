@@ -883,11 +883,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MC_MS_WAVES_
                 const double F = S::bcast(U, 0) / kMlMinPerLs;
                 U = S::next(U, U, N);   // shift: u_k <- u_{k+1}, the last one kept
                 if (out.tu && kid == 0) out.tu[(int64_t)i * out.S + pos] = F;
+                // the plant runs alike on every lane of the segment: lane k
+                // draws the noise of sub-step j0 + k, and each sub-step takes
+                // its normals from the lane that drew them (a lane past the
+                // last sub-step draws a value nobody uses)
                 #pragma unroll 1
-                for (int j = 0; j < p.Ns; ++j) {
-                    double xi[3];
-                    process_noise(p, (uint32_t)(i * p.Ns + j), su.nid, xi);
-                    em_step(p, su.k0, su.EaR, n, F, h, sqh, xi);
+                for (int j0 = 0; j0 < p.Ns; j0 += G) {
+                    double own[3];
+                    process_noise(p, (uint32_t)(i * p.Ns + j0 + kid), su.nid, own);
+                    const int jn = p.Ns - j0 < G ? p.Ns - j0 : G;
+                    #pragma unroll 1
+                    for (int j = 0; j < jn; ++j) {
+                        const double xi[3] = {S::bcast(own[0], j), S::bcast(own[1], j),
+                                              S::bcast(own[2], j)};
+                        em_step(p, su.k0, su.EaR, n, F, h, sqh, xi);
+                    }
                 }
                 Fprev = F;
                 ++i;
