@@ -840,10 +840,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NMAX == 64 ?
     }
 }
 
-// PI closed loop, eq. (PI), one sample per lane.  With ck != null the plant
-// state (n, I-hat) at the start of every interval i = 0, C, 2C, ... is kept
-// for the reverse pass: ck[((i / C) * 4 + f) * npi + t].  With ctl != null
-// the launch covers the PI samples [c ppc, (c + 1) ppc) of chunk c = *ctl.
 // K lanes per PI sample.  A PI closed loop is one serial chain, so a launch
 // with fewer wavefronts than SIMDs takes one chain's time, and most of a
 // sub-step's instructions draw its noise (Philox, Box-Muller), which does
@@ -888,6 +884,11 @@ __device__ __forceinline__ void pi_substeps(const DevParams& p, const Setup& su,
     }
 }
 
+// PI closed loop, eq. (PI), one sample per group of K lanes (sample t on
+// lanes [K t, K (t + 1)) of the launch).  With ck != null the plant state
+// (n, I-hat) at the start of every interval i = 0, C, 2C, ... is kept for
+// the reverse pass: ck[((i / C) * 4 + f) * npi + t].  With ctl != null the
+// launch covers the PI samples [c ppc, (c + 1) ppc) of chunk c = *ctl.
 template <int K>
 __global__ __launch_bounds__(64) void pi_kernel(DevParams p, const int64_t* pos_list, int64_t npi,
                                                 Outs out, double* ck, const int* ctl, int64_t ppc) {
@@ -975,8 +976,8 @@ __global__ __launch_bounds__(64) void pi_kernel(DevParams p, const int64_t* pos_
 // per-sub-step states and noise taped (tape[(step * 6 + f) * npi + t]),
 // then swept backwards.  (Drawing the noise again in the reverse sweep
 // instead of taping it halves the tape but adds two Philox blocks and a
-// Box-Muller pair to each lane's serial chain: c2's reverse pass took
-// 48.9 ms that way against 35.1 ms taped.)  Writes dPhi/dkP and dPhi/dkI
+// Box-Muller pair to each sample's serial chain: with one lane per sample,
+// c2's reverse pass took 48.9 ms that way against 35.1 ms taped.)  Writes dPhi/dkP and dPhi/dkI
 // per sample.  A sample takes K lanes as in pi_kernel: the recomputation
 // draws the noise of K sub-steps at once, and the K lanes tape, sweep and
 // write the same values.

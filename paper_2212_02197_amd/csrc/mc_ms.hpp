@@ -23,10 +23,10 @@
 //     interior point's element-wise steps run on all stages at once, with
 //     a stage's neighbours fetched by lane shifts;
 //   * the stage recursions of the Riccati solve are parallel prefix scans
-//     over the lanes (log2 N steps): the scalar Riccati recursion of the
-//     factor P_k is a linear-fractional map of P_{k+1}, composed as 2x2
-//     matrices, and the recursions of the Riccati vector and of the
-//     forward state steps are affine maps;
+//     over the segment's lanes (log2 G steps): the scalar Riccati
+//     recursion of the factor P_k is a linear-fractional map of P_{k+1},
+//     composed as 2x2 matrices, and the recursions of the Riccati vector
+//     and of the forward state steps are affine maps;
 //   * sums and maxima over the stages are segment reductions.
 // Only the feasible start of each OCP, where the states follow the inputs
 // through the model, runs the stages one after another.
