@@ -480,21 +480,26 @@ __device__ __forceinline__ int ms_qp_lanes(const DevParams& p, int N, MsStage s,
         const double rx = wdx + fxp - mu * s.A + mup;
         const double dxN = S::bcast(dx, N - 1), muN = S::bcast(mu, N - 1);
         const double rxN = PN * dxN + fxN + muN;
-        double rl = act ? fabs(ru) : 0.0, wl = act ? fabs(wdu) : 0.0;
-        if (hasx) {
-            rl = fmax(rl, fabs(rx));
-            wl = fmax(wl, fabs(wdx));
-        }
-        const double rmax = fmax(fabs(rxN), S::max(rl));
-        const double wd = fmax(fabs(PN * dxN), S::max(wl));
         const double comp = S::sum(act ? tl * nl + tu * nu : 0.0);
         // the stopping test reads the residuals alone: it comes before the
-        // factorisation, which a converged or capped iterate does not need
+        // factorisation, which a converged or capped iterate does not need.
+        // It needs both its parts, so the residual maxima are taken only
+        // once the complementarity part holds (which it does in the last
+        // iterations only; its sum is the same on the whole segment)
         const double muc = comp * inv2N;
-        if (rmax <= 1e-12 * (1.0 + gsc + wd) && muc <= 1e-14 * (1.0 + gsc)) {
-            iters = it;
-            o = MsQpOut{du, dx, mu, nl, nu};
-            return 0;
+        if (muc <= 1e-14 * (1.0 + gsc)) {
+            double rl = act ? fabs(ru) : 0.0, wl = act ? fabs(wdu) : 0.0;
+            if (hasx) {
+                rl = fmax(rl, fabs(rx));
+                wl = fmax(wl, fabs(wdx));
+            }
+            const double rmax = fmax(fabs(rxN), S::max(rl));
+            const double wd = fmax(fabs(PN * dxN), S::max(wl));
+            if (rmax <= 1e-12 * (1.0 + gsc + wd)) {
+                iters = it;
+                o = MsQpOut{du, dx, mu, nl, nu};
+                return 0;
+            }
         }
         if (it == p.ipm_max_iter) {
             iters = it;
