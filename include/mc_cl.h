@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define MC_CL_ABI_VERSION 5u
+#define MC_CL_ABI_VERSION 6u
 #define MC_CL_SPMAX 8        /* setpoint schedule levels                        */
 #define MC_CL_NMAX 64        /* largest NMPC horizon                            */
 #define MC_CL_NHIST 202      /* histogram: underflow, 200 bins, overflow        */
@@ -304,14 +304,19 @@ int mc_cl_plan(mc_cl_ctx *c, int32_t *out, int max_classes);
  * campaign with want_grad and PI samples, times the PI forward pass with
  * checkpoints plus the reverse pass at each candidate checkpoint interval
  * C (2, 5, 10, 25, 50; those above the longest sample's L skipped,
- * time -1) and keeps the fastest.  Phi and the counters are bitwise the
- * same for every launch shape; C moves the gradient by rounding only (each
- * segment is recomputed from its checkpoint).  Synchronises `hip_stream`; the trial launches overwrite the last
+ * time -1) and keeps the fastest; for a campaign with PI samples, times
+ * the PI pass (with the reverse pass at the chosen C when the gradient is
+ * wanted) with 1, 2 and 4 lanes per sample and keeps the fastest (without
+ * tuning the library takes the most lanes that keep the PI launch at one
+ * wavefront per SIMD).  Phi, the counters and the gradient are bitwise the
+ * same for every launch shape and lane count; C moves the gradient by
+ * rounding only (each segment is recomputed from its checkpoint).  Synchronises `hip_stream`; the trial launches overwrite the last
  * run's results, so mc_cl_costs / mc_cl_grad need a new mc_cl_run.  The
  * workspaces grow to the largest candidate tried.  EINVAL for a null
  * argument or trial_intervals < 1; ENOMEM, EHIP.                           */
 #define MC_CL_TUNE_NSPW 5
 #define MC_CL_TUNE_NCK 5
+#define MC_CL_TUNE_NPIK 3
 typedef struct {
     int32_t n_classes;
     int32_t nmax[3];                      /* NMAX of each horizon class      */
@@ -319,6 +324,9 @@ typedef struct {
     float nmpc_ms[3][MC_CL_TUNE_NSPW];    /* trial time per candidate        */
     int32_t ckpt_interval;                /* chosen C (0: no PI gradient)    */
     float grad_ms[MC_CL_TUNE_NCK];        /* trial time per candidate C      */
+    int32_t pi_lanes;                     /* chosen lanes per PI sample (0:
+                                             no PI samples)                  */
+    float pi_ms[MC_CL_TUNE_NPIK];         /* trial time at 1, 2, 4 lanes     */
 } mc_cl_tune_result;
 int mc_cl_tune(mc_cl_ctx *c, void *hip_stream, int32_t trial_intervals, mc_cl_tune_result *r);
 

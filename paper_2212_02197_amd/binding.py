@@ -20,7 +20,7 @@ CNT_NAMES = ["kind", "N", "L", "n_ocp", "n_ocp_fail", "sqp_iter", "ipm_iter", "l
 NCNT = len(CNT_NAMES)
 STATUS = {0: "MC_CL_OK", -1: "MC_CL_EINVAL", -2: "MC_CL_EHIP", -3: "MC_CL_ENOMEM",
           -4: "MC_CL_ESTATE", -5: "MC_CL_EUNSUPPORTED"}
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 
 class Params(C.Structure):
@@ -74,12 +74,14 @@ class Stats(C.Structure):
 
 TUNE_SPW = (4, 8, 16, 32, 64)
 TUNE_CKPT = (2, 5, 10, 25, 50)
+TUNE_PI_LANES = (1, 2, 4)
 
 
 class TuneResult(C.Structure):
     _fields_ = [("n_classes", C.c_int32), ("nmax", C.c_int32 * 3), ("spw", C.c_int32 * 3),
                 ("nmpc_ms", (C.c_float * len(TUNE_SPW)) * 3), ("ckpt_interval", C.c_int32),
-                ("grad_ms", C.c_float * len(TUNE_CKPT))]
+                ("grad_ms", C.c_float * len(TUNE_CKPT)), ("pi_lanes", C.c_int32),
+                ("pi_ms", C.c_float * len(TUNE_PI_LANES))]
 
 
 EXPORTS = ["mc_cl_create", "mc_cl_run", "mc_cl_costs", "mc_cl_grad", "mc_cl_destroy",
@@ -304,7 +306,8 @@ class Campaign:
 
     def tune(self, trial_intervals: int = 6, stream=None):
         """mc_cl_tune: measured samples-per-wavefront (and PI checkpoint
-        interval) choice; returns the trial times and the choice."""
+        interval and lanes-per-sample) choice; returns the trial times and
+        the choice."""
         st = stream if stream is not None else self.torch.cuda.current_stream()
         r = TuneResult()
         _check(lib().mc_cl_tune(self.h, C.c_void_p(st.cuda_stream), int(trial_intervals),
@@ -315,7 +318,9 @@ class Campaign:
                           trial_ms={s: round(float(r.nmpc_ms[k][j]), 3)
                                     for j, s in enumerate(TUNE_SPW)}) for k in range(n)],
             ckpt_interval=r.ckpt_interval,
-            grad_trial_ms={c: round(float(r.grad_ms[j]), 3) for j, c in enumerate(TUNE_CKPT)})
+            grad_trial_ms={c: round(float(r.grad_ms[j]), 3) for j, c in enumerate(TUNE_CKPT)},
+            pi_lanes=r.pi_lanes,
+            pi_trial_ms={k: round(float(r.pi_ms[j]), 3) for j, k in enumerate(TUNE_PI_LANES)})
 
     def plan(self):
         buf = (C.c_int32 * 15)()

@@ -102,20 +102,18 @@ int pi_lanes(int64_t n, int n_cu) {
     return 1;
 }
 // The PI forward pass over n samples (a chunk's with ctl, else the first n
-// of pos).
-hipError_t launch_pi(int n_cu, int64_t n, hipStream_t st, const DevParams& dp, const int64_t* pos,
+// of pos) with k lanes per sample.
+hipError_t launch_pi(int k, int64_t n, hipStream_t st, const DevParams& dp, const int64_t* pos,
                      int64_t npi, const Outs& o, double* ck, const int* ctl, int64_t ppc) {
-    const int k = pi_lanes(n, n_cu);
     const dim3 grid((unsigned)((n * k + 63) / 64)), block(64);
     if (k == 4) hipLaunchKernelGGL(pi_kernel<4>, grid, block, 0, st, dp, pos, npi, o, ck, ctl, ppc);
     else if (k == 2) hipLaunchKernelGGL(pi_kernel<2>, grid, block, 0, st, dp, pos, npi, o, ck, ctl, ppc);
     else hipLaunchKernelGGL(pi_kernel<1>, grid, block, 0, st, dp, pos, npi, o, ck, ctl, ppc);
     return hipGetLastError();
 }
-hipError_t launch_pi_reverse(int n_cu, hipStream_t st, const DevParams& dp, const int64_t* pos,
+hipError_t launch_pi_reverse(int k, hipStream_t st, const DevParams& dp, const int64_t* pos,
                              int64_t npi, const double* ck, double* tape, double* ivtape,
                              double* gk) {
-    const int k = pi_lanes(npi, n_cu);
     const dim3 grid((unsigned)((npi * k + 63) / 64)), block(64);
     if (k == 4)
         hipLaunchKernelGGL(pi_reverse_kernel<4>, grid, block, 0, st, dp, pos, npi, ck, tape, ivtape, gk);
@@ -293,6 +291,8 @@ struct mc_cl_ctx {
     double* d_stats = nullptr;
     unsigned long long* d_hist = nullptr;
     long long* d_totals = nullptr;
+    // lanes per PI sample chosen by mc_cl_tune (0: pi_lanes' choice)
+    int pi_k = 0;
     // PI reverse pass
     int ckC = 0;
     double* d_ck = nullptr;
@@ -389,6 +389,10 @@ struct mc_cl_ctx {
         return MC_CL_OK;
     }
 };
+
+// Lanes per PI sample for a launch over n samples: the tuned choice, else
+// pi_lanes' rule.
+static int pi_k_of(const mc_cl_ctx* c, int64_t n) { return c->pi_k > 0 ? c->pi_k : pi_lanes(n, c->n_cu); }
 
 static int validate(const mc_cl_params* p) {
     if (!p) return MC_CL_EINVAL;
@@ -555,7 +559,7 @@ static int launch_step(mc_cl_ctx* c, hipStream_t st, const Outs& out, bool chunk
     if (ev_mid) HIPCHK(hipEventRecord(ev_mid, st));
     if (c->n_pi) {
         const int64_t n = chunk ? c->pi_per_chunk : c->n_pi;
-        HIPCHK(launch_pi(c->n_cu, n, st, c->dp, c->d_pos_pi, c->n_pi, out, c->d_ck,
+        HIPCHK(launch_pi(pi_k_of(c, n), n, st, c->dp, c->d_pos_pi, c->n_pi, out, c->d_ck,
                          chunk ? c->d_ctl : nullptr, c->pi_per_chunk));
     }
     if (chunk) {
@@ -913,8 +917,8 @@ int mc_cl_grad(mc_cl_ctx* c, void* hip_stream, double g[2], double* per_sample) 
     HIPCHK(hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)hip_stream;
     HIPCHK(hipEventRecord(c->ev[4], st));
-    HIPCHK(launch_pi_reverse(c->n_cu, st, c->dp, c->d_pos_pi, c->n_pi, c->d_ck, c->d_tape,
-                             c->d_ivtape, c->d_gk));
+    HIPCHK(launch_pi_reverse(pi_k_of(c, c->n_pi), st, c->dp, c->d_pos_pi, c->n_pi, c->d_ck,
+                             c->d_tape, c->d_ivtape, c->d_gk));
     hipLaunchKernelGGL(grad_reduce_kernel, dim3(1), dim3(1024), 0, st, c->d_gk, c->n_pi, c->d_gsum);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(c->ev[5], st));
@@ -1038,10 +1042,10 @@ int mc_cl_tune(mc_cl_ctx* c, void* hip_stream, int32_t trial_intervals, mc_cl_tu
             if ((rc = size_ckpt(c, kCk[j])) != MC_CL_OK) break;
             float ms = 0.0f;
             rc = timed([&]() -> int {
-                HIPCHK(launch_pi(c->n_cu, c->n_pi, st, c->dp, c->d_pos_pi, c->n_pi, out, c->d_ck,
-                                 nullptr, (int64_t)0));
-                HIPCHK(launch_pi_reverse(c->n_cu, st, c->dp, c->d_pos_pi, c->n_pi, c->d_ck,
-                                         c->d_tape, c->d_ivtape, c->d_gk));
+                HIPCHK(launch_pi(pi_k_of(c, c->n_pi), c->n_pi, st, c->dp, c->d_pos_pi, c->n_pi,
+                                 out, c->d_ck, nullptr, (int64_t)0));
+                HIPCHK(launch_pi_reverse(pi_k_of(c, c->n_pi), st, c->dp, c->d_pos_pi, c->n_pi,
+                                         c->d_ck, c->d_tape, c->d_ivtape, c->d_gk));
                 return MC_CL_OK;
             }, ms);
             r->grad_ms[j] = ms;
@@ -1052,6 +1056,33 @@ int mc_cl_tune(mc_cl_ctx* c, void* hip_stream, int32_t trial_intervals, mc_cl_tu
         }
         if (rc == MC_CL_OK) rc = size_ckpt(c, bC);
         r->ckpt_interval = c->ckC;
+    }
+    // PI: lanes per sample, the whole PI pass (with the reverse pass at the
+    // chosen C when the gradient is wanted) at each candidate; the results
+    // are bitwise the same for every lane count
+    if (rc == MC_CL_OK && c->n_pi) {
+        static const int kK[MC_CL_TUNE_NPIK] = {1, 2, 4};
+        const bool grad = c->prm.want_grad && c->d_ck;
+        float best = INFINITY;
+        int bk = pi_lanes(c->n_pi, c->n_cu);
+        for (int j = 0; j < MC_CL_TUNE_NPIK && rc == MC_CL_OK; ++j) {
+            float ms = 0.0f;
+            rc = timed([&]() -> int {
+                HIPCHK(launch_pi(kK[j], c->n_pi, st, c->dp, c->d_pos_pi, c->n_pi, out,
+                                 grad ? c->d_ck : nullptr, nullptr, (int64_t)0));
+                if (grad)
+                    HIPCHK(launch_pi_reverse(kK[j], st, c->dp, c->d_pos_pi, c->n_pi, c->d_ck,
+                                             c->d_tape, c->d_ivtape, c->d_gk));
+                return MC_CL_OK;
+            }, ms);
+            r->pi_ms[j] = ms;
+            if (rc == MC_CL_OK && ms < best) {
+                best = ms;
+                bk = kK[j];
+            }
+        }
+        if (rc == MC_CL_OK) c->pi_k = bk;
+        r->pi_lanes = bk;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1211,8 +1242,8 @@ int mc_cl_run_static(const mc_cl_params* p, void* hip_stream, const mc_cl_output
         off += count;
     }
     if (counts[3] > 0) {
-        HIPCHK(launch_pi(n_cu, (int64_t)counts[3], st, dp, d_pos + off, (int64_t)counts[3], out,
-                         nullptr, nullptr, (int64_t)0));
+        HIPCHK(launch_pi(pi_lanes((int64_t)counts[3], n_cu), (int64_t)counts[3], st, dp, d_pos + off,
+                         (int64_t)counts[3], out, nullptr, nullptr, (int64_t)0));
     }
     return MC_CL_OK;
 }

@@ -536,6 +536,9 @@ def test_tune_keeps_results_and_picks_a_candidate():
     assert 1 <= res["classes"][0]["spw"] <= max(binding.TUNE_SPW)
     assert all(v > 0 for v in res["classes"][0]["trial_ms"].values())
     assert res["ckpt_interval"] in binding.TUNE_CKPT
+    # lanes per PI sample: the 100 PI samples timed at 1, 2 and 4 lanes
+    assert res["pi_lanes"] in binding.TUNE_PI_LANES
+    assert all(v > 0 for v in res["pi_trial_ms"].values())
     assert camp.plan()[0]["spw"] == res["classes"][0]["spw"]
     camp.run()
     phi, st = camp.costs()
