@@ -883,6 +883,20 @@ __device__ __forceinline__ void pi_substeps(const DevParams& p, const Setup& su,
         pi_group_steps<K, 0>(j0, p.Ns, own, step);
     }
 }
+// The reverse sweep's counterpart: sub-steps j0, j0 - 1, ..., j0 - K + 1
+// (those >= 0) in turn, each with the M values lane r = j0 - j formed.
+template <int K, int RR, int M, class Step>
+__device__ __forceinline__ void pi_group_back(int j0, const double (&own)[M], Step& step) {
+    if constexpr (RR < K) {
+        if (j0 - RR >= 0) {   // the same on every lane
+            double v[M];
+#pragma unroll
+            for (int q = 0; q < M; ++q) v[q] = group_bcast<K, RR>(own[q]);
+            step(v);
+        }
+        pi_group_back<K, RR + 1>(j0, own, step);
+    }
+}
 
 // PI closed loop, eq. (PI), one sample per group of K lanes (sample t on
 // lanes [K t, K (t + 1)) of the launch).  With ck != null the plant state
@@ -1065,10 +1079,27 @@ __global__ __launch_bounds__(64) void pi_reverse_kernel(DevParams p, const int64
             if (uk > p.pi_umax) uk = p.pi_umax;
             if (uk < p.pi_umin) uk = p.pi_umin;
             const bool inside = (uh > p.pi_umin && uh < p.pi_umax);
-            // plant: Ns Euler-Maruyama sub-steps backwards
+            // plant: Ns Euler-Maruyama sub-steps backwards, K at a time: lane
+            // r reads the tape of sub-step j0 - r and forms its values that
+            // do not depend on the adjoint (the rate's derivatives and the
+            // input sensitivity), all K at once; the K lanes then apply the
+            // sub-steps' transposed Jacobians in turn
             double Fb = 0.0;
+            auto back = [&](const double (&cf)[6]) {
+                // J^T nb with J = -F/V I + S dr^T V
+                const double Snb = -nb[0] - 2.0 * nb[1] + p.beta * nb[2];
+                const double m0 = nb[0] + h * (-uk * iV * nb[0] + cf[0] * Snb);
+                const double m1 = nb[1] + h * (-uk * iV * nb[1] + cf[1] * Snb);
+                const double m2 = nb[2] + h * (-uk * iV * nb[2] + cf[2] * Snb);
+                Fb += nb[0] * cf[3] + nb[1] * cf[4] + nb[2] * cf[5];
+                nb[0] = m0; nb[1] = m1; nb[2] = m2;
+            };
+            const int r = (int)threadIdx.x & (K - 1);
             #pragma unroll 1
-            for (int j = p.Ns - 1; j >= 0; --j) {
+            for (int j0 = p.Ns - 1; j0 >= 0; j0 -= K) {
+                // a lane past sub-step 0 reads sub-step 0's tape; what it
+                // forms is not used
+                const int j = j0 - r >= 0 ? j0 - r : 0;
                 const int64_t st = (int64_t)li * p.Ns + j;
                 const double a0 = tape[(st * 6 + 0) * npi + t];
                 const double a1 = tape[(st * 6 + 1) * npi + t];
@@ -1078,19 +1109,14 @@ __global__ __launch_bounds__(64) void pi_reverse_kernel(DevParams p, const int64
                 const double x2 = tape[(st * 6 + 5) * npi + t];
                 const double cA = a0 * iV, cB = a1 * iV, cT = a2 * iV;
                 const double k = su.k0 * exp(-su.EaR / cT);
-                // dr/dn = (k cB, k cA, k EaR/cT^2 cA cB) / V ; (S r V) rows S
-                const double dr0 = k * cB * iV, dr1 = k * cA * iV;
-                const double dr2 = k * (su.EaR / (cT * cT)) * cA * cB * iV;
-                // J^T nb with J = -F/V I + S dr^T V
-                const double Snb = -nb[0] - 2.0 * nb[1] + p.beta * nb[2];
-                const double m0 = nb[0] + h * (-uk * iV * nb[0] + dr0 * p.V * Snb);
-                const double m1 = nb[1] + h * (-uk * iV * nb[1] + dr1 * p.V * Snb);
-                const double m2 = nb[2] + h * (-uk * iV * nb[2] + dr2 * p.V * Snb);
-                // dn+/dF = h (C_in - c) + sigma sqrt(h) xi
-                Fb += nb[0] * (h * (p.cAin - cA) + p.sig[0] * sqh * x0) +
-                      nb[1] * (h * (p.cBin - cB) + p.sig[1] * sqh * x1) +
-                      nb[2] * (h * (p.cTin - cT) + p.sig[2] * sqh * x2);
-                nb[0] = m0; nb[1] = m1; nb[2] = m2;
+                // dr/dn = (k cB, k cA, k EaR/cT^2 cA cB) / V, times V for the
+                // rows of S r V; dn+/dF = h (C_in - c) + sigma sqrt(h) xi
+                const double cf[6] = {k * cB * iV * p.V, k * cA * iV * p.V,
+                                      k * (su.EaR / (cT * cT)) * cA * cB * iV * p.V,
+                                      h * (p.cAin - cA) + p.sig[0] * sqh * x0,
+                                      h * (p.cBin - cB) + p.sig[1] * sqh * x1,
+                                      h * (p.cTin - cT) + p.sig[2] * sqh * x2};
+                pi_group_back<K, 0>(j0, cf, back);
             }
             // PI law backwards: I-hat_i = I + Ts kaw (uh - u)
             const double ub = Fb - Ib * p.Ts * p.kaw;
