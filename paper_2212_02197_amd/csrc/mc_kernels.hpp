@@ -857,6 +857,19 @@ __device__ __forceinline__ double group_bcast(double v) {
     else if constexpr (K == 2) return dpp_z<RR | RR << 2 | (2 + RR) << 4 | (2 + RR) << 6>(v);
     else return dpp_z<RR * 0x55>(v);   // quad_perm [RR, RR, RR, RR]
 }
+// The value that lane q of the group holds, on the whole group (q the same
+// on every lane): a group draws per-interval noise for K intervals at once,
+// lane q that of the q-th.
+template <int K>
+__device__ __forceinline__ double group_pick(double v, int q) {
+    if constexpr (K == 1) return v;
+    else if constexpr (K == 2) return q == 0 ? group_bcast<2, 0>(v) : group_bcast<2, 1>(v);
+    else {
+        const double v0 = group_bcast<4, 0>(v), v1 = group_bcast<4, 1>(v);
+        const double v2 = group_bcast<4, 2>(v), v3 = group_bcast<4, 3>(v);
+        return q == 0 ? v0 : (q == 1 ? v1 : (q == 2 ? v2 : v3));
+    }
+}
 template <int K, int RR, class Step>
 __device__ __forceinline__ void pi_group_steps(int j0, int Ns, const double (&own)[3], Step& step) {
     if constexpr (RR < K) {
@@ -934,6 +947,7 @@ __global__ __launch_bounds__(64) void pi_kernel(DevParams p, const int64_t* pos_
         }
     }
     int nonfin = 0;
+    double meas = 0.0;   // measurement noise drawn for the group (below)
     for (int i = 0;; ++i) {
         const double z = n[2] / p.V;
         const double zb = setpoint(p, i, su.istep, su.sign);
@@ -947,8 +961,12 @@ __global__ __launch_bounds__(64) void pi_kernel(DevParams p, const int64_t* pos_
             ck[(b + 2) * npi + t] = n[2];
             ck[(b + 3) * npi + t] = Ihat;
         }
-        const double y = z + p.noise_scale * sqrtR *
-                                 normal_first(p.seed, 0, (uint32_t)i, su.nid, kTagMeas);
+        // the measurement noise of intervals i .. i + K - 1, lane r that of
+        // i + r (i is the same on every lane still running)
+        if ((i & (K - 1)) == 0)
+            meas = normal_first(p.seed, 0, (uint32_t)(i + ((int)threadIdx.x & (K - 1))), su.nid,
+                                kTagMeas);
+        const double y = z + p.noise_scale * sqrtR * group_pick<K>(meas, i & (K - 1));
         if (p.run_ekf_for_pi && p.model_nx == 3) {
             ekf3_predict(p, x3, P3, Fprev);
             ekf3_update(p, x3, P3, y);
@@ -1024,12 +1042,16 @@ __global__ __launch_bounds__(64) void pi_reverse_kernel(DevParams p, const int64
                        ck[((int64_t)sgi * 4 + 2) * npi + t]};
         double Ihat = ck[((int64_t)sgi * 4 + 3) * npi + t];
         // forward recompute of the segment, taping
+        double meas = 0.0;
         #pragma unroll 1
         for (int i = i0; i < i1; ++i) {
             const int li = i - i0;
             const double z = n[2] * iV;
-            const double xm = p.noise_scale * sqrtR *
-                              normal_first(p.seed, 0, (uint32_t)i, su.nid, kTagMeas);
+            // the measurement noise of K intervals at once, as in pi_kernel
+            if ((li & (K - 1)) == 0)
+                meas = normal_first(p.seed, 0, (uint32_t)(i + ((int)threadIdx.x & (K - 1))), su.nid,
+                                    kTagMeas);
+            const double xm = p.noise_scale * sqrtR * group_pick<K>(meas, li & (K - 1));
             iv_tape[((int64_t)li * 5 + 0) * npi + t] = n[0];
             iv_tape[((int64_t)li * 5 + 1) * npi + t] = n[1];
             iv_tape[((int64_t)li * 5 + 2) * npi + t] = n[2];
